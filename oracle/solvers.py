@@ -1,0 +1,333 @@
+"""FP64 Krylov solvers of the oracle: CGLS, LSQR, LSMR, hybrid LSQR, IRN-TV.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+
+Every solver is matrix-free: it takes callables ``A(x)`` and ``AT(y)`` that
+apply the operator and its transpose, works in float64 NumPy, starts from
+x0 = 0 unless told otherwise, and runs a fixed number of iterations.  Each
+returns ``(x, hist)`` where ``hist`` holds per-iteration FP64 scalars.
+
+Sources (the paper states the objectives; the recurrences are those of the
+works it cites for each method).  Equations are named by their labels:
+  * CGLS      -- Sec. 2.1.1, eq. (lest_squares_projected): CG on the normal
+                 equations (Hestenes and Stiefel); with damping lambda it solves
+                 the Tikhonov problem, eq. (Tikhonov), via the augmented system
+                 of eq. (Tikhonov_augmented).
+  * LSQR      -- Sec. 2.1.2, eq. (proj_LSQR): Golub-Kahan bidiagonalisation and
+                 the short recurrences of Paige and Saunders (1982), damped form.
+  * LSMR      -- Sec. 2.1.3, eq. (proj_LSMR): minimises ||A^T r_k|| over the
+                 same Krylov space (Fong and Saunders 2011), damped form.
+  * hybrid    -- Sec. 2.2.1, eq. (hybrid_LSQR): Tikhonov on the projected
+                 problem with a fixed lambda, solved densely on the stored
+                 bidiagonal matrix.
+  * IRN-TV    -- Sec. 2.3, eqs. (TV), (TV_reweighted), (TV_approx) and
+                 Sec. 2.3.1: reweighted quadratic majorants of isotropic TV, each
+                 solved by CGLS on [A; lam L D].
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def _dot(a, b):
+    return float(np.dot(a.ravel(), b.ravel()))
+
+
+def _nrm(a):
+    return float(np.sqrt(np.dot(a.ravel(), a.ravel())))
+
+
+# --------------------------------------------------------------------------
+# CGLS (Sec. 2.1.1): x_k minimises ||A x - b|| over K_k(A^T A, A^T b).
+# --------------------------------------------------------------------------
+def cgls(A, AT, b, n_iter, lam=0.0, x0=None):
+    """Conjugate gradients on (A^T A + lam^2 I) x = A^T b.
+
+    hist: 'res' = ||b - A x_k|| (the data residual, recurred), 'res_damped' =
+    sqrt(||r||^2 + lam^2 ||x||^2), 'normal' = ||A^T r_k - lam^2 x_k||,
+    'alpha', 'beta'.
+    """
+    b = np.asarray(b, dtype=np.float64)
+    lam2 = float(lam) ** 2
+    if x0 is None:
+        x = np.zeros_like(AT(b))
+        r = b.copy()
+    else:
+        x = np.array(x0, dtype=np.float64)
+        r = b - A(x)
+    s = AT(r) - lam2 * x
+    p = s.copy()
+    gamma = _dot(s, s)
+    hist = {"res": [], "res_damped": [], "normal": [], "alpha": [], "beta": []}
+    for _ in range(n_iter):
+        if gamma == 0.0:
+            break
+        q = A(p)
+        delta = _dot(q, q) + lam2 * _dot(p, p)
+        alpha = gamma / delta
+        x = x + alpha * p
+        r = r - alpha * q
+        s = AT(r) - lam2 * x
+        gamma_new = _dot(s, s)
+        beta = gamma_new / gamma
+        gamma = gamma_new
+        p = s + beta * p
+        rn = _nrm(r)
+        hist["res"].append(rn)
+        hist["res_damped"].append(np.sqrt(rn * rn + lam2 * _dot(x, x)))
+        hist["normal"].append(np.sqrt(gamma))
+        hist["alpha"].append(alpha)
+        hist["beta"].append(beta)
+    return x, {k: np.asarray(v) for k, v in hist.items()}
+
+
+# --------------------------------------------------------------------------
+# Golub-Kahan bidiagonalisation (Sec. 2.1.2): A V_k = U_{k+1} B_k.
+# --------------------------------------------------------------------------
+def _normalise(w):
+    n = _nrm(w)
+    return (w / n if n > 0.0 else w * 0.0), n
+
+
+def lsqr(A, AT, b, n_iter, lam=0.0):
+    """LSQR with damping ``lam`` (Paige and Saunders, Sec. 2.1.2 / Sec. 2.2).
+
+    Iterates x_k minimise ||[A; lam I] x - [b; 0]|| over K_k.  hist: 'res'
+    (recurred ||[b;0] - [A;lam I] x_k||), 'alpha', 'beta' (the bidiagonal
+    entries alpha_{k+1}, beta_{k+1} produced in iteration k).
+    """
+    b = np.asarray(b, dtype=np.float64)
+    u, beta = _normalise(b.copy())
+    v, alpha = _normalise(AT(u))
+    x = np.zeros_like(v)
+    w = v.copy()
+    phibar, rhobar = beta, alpha
+    psi_sq = 0.0
+    hist = {"res": [], "alpha": [], "beta": []}
+    for _ in range(n_iter):
+        if alpha == 0.0 or beta == 0.0:
+            break
+        # Bidiagonalisation: beta_{k+1} u_{k+1} = A v_k - alpha_k u_k, then
+        # alpha_{k+1} v_{k+1} = A^T u_{k+1} - beta_{k+1} v_k.
+        u, beta = _normalise(A(v) - alpha * u)
+        v, alpha = _normalise(AT(u) - beta * v)
+        # Rotation that folds the damping row lam into rhobar.
+        rhohat = np.hypot(rhobar, lam)
+        c1, s1 = rhobar / rhohat, lam / rhohat
+        psi = s1 * phibar
+        phibar = c1 * phibar
+        psi_sq += psi * psi
+        # Rotation that eliminates beta_{k+1} from the bidiagonal.
+        rho = np.hypot(rhohat, beta)
+        c, s = rhohat / rho, beta / rho
+        theta = s * alpha
+        rhobar = -c * alpha
+        phi = c * phibar
+        phibar = s * phibar
+        x = x + (phi / rho) * w
+        w = v - (theta / rho) * w
+        hist["res"].append(np.sqrt(phibar * phibar + psi_sq))
+        hist["alpha"].append(alpha)
+        hist["beta"].append(beta)
+    return x, {k: np.asarray(v) for k, v in hist.items()}
+
+
+def lsmr(A, AT, b, n_iter, lam=0.0):
+    """LSMR with damping ``lam`` (Fong and Saunders, Sec. 2.1.3).
+
+    Iterates x_k minimise ||A_lam^T r_k|| over K_k, where A_lam = [A; lam I]
+    and r_k = [b; 0] - A_lam x_k.  hist: 'normal' = recurred ||A_lam^T r_k||
+    (= |zetabar_{k+1}|), 'alpha', 'beta'.
+    """
+    b = np.asarray(b, dtype=np.float64)
+    u, beta = _normalise(b.copy())
+    v, alpha = _normalise(AT(u))
+    x = np.zeros_like(v)
+    h = v.copy()
+    hbar = np.zeros_like(v)
+    alphabar = alpha
+    zetabar = alpha * beta
+    rho_old, rhobar_old = 1.0, 1.0
+    cbar, sbar = 1.0, 0.0
+    hist = {"normal": [], "alpha": [], "beta": []}
+    for _ in range(n_iter):
+        if alpha == 0.0 or beta == 0.0:
+            break
+        u, beta = _normalise(A(v) - alpha * u)
+        v, alpha = _normalise(AT(u) - beta * v)
+        # Fold the damping into alphabar (first rotation of the damped problem).
+        alphahat = np.hypot(alphabar, lam)
+        # Rotation P_k: eliminate beta_{k+1} from the lower bidiagonal.
+        rho = np.hypot(alphahat, beta)
+        c, s = alphahat / rho, beta / rho
+        theta_next = s * alpha
+        alphabar = c * alpha
+        # Rotation Pbar_k: turn R_k^T into lower bidiagonal form.
+        thetabar = sbar * rho
+        rhobar = np.hypot(cbar * rho, theta_next)
+        cbar_new = cbar * rho / rhobar
+        sbar = theta_next / rhobar
+        zeta = cbar_new * zetabar
+        zetabar = -sbar * zetabar
+        cbar = cbar_new
+        # Vector updates.
+        hbar = h - (thetabar * rho / (rho_old * rhobar_old)) * hbar
+        x = x + (zeta / (rho * rhobar)) * hbar
+        h = v - (theta_next / rho) * h
+        rho_old, rhobar_old = rho, rhobar
+        hist["normal"].append(abs(zetabar))
+        hist["alpha"].append(alpha)
+        hist["beta"].append(beta)
+    return x, {k: np.asarray(v) for k, v in hist.items()}
+
+
+# --------------------------------------------------------------------------
+# Hybrid LSQR with a fixed lambda (Sec. 2.2.1, eq. (hybrid_LSQR)).
+# --------------------------------------------------------------------------
+def golub_kahan(A, AT, b, k):
+    """k steps of GK: returns (U (k+1 vectors), V (k vectors), B (k+1 x k), beta1).
+
+    A V_k = U_{k+1} B_k with B_k lower bidiagonal: B[i, i] = alpha_{i+1},
+    B[i+1, i] = beta_{i+2}.  Stops early on breakdown.
+    """
+    b = np.asarray(b, dtype=np.float64)
+    u, beta1 = _normalise(b.copy())
+    v, alpha = _normalise(AT(u))
+    Us, Vs = [u], []
+    alphas, betas = [], []
+    for _ in range(k):
+        if alpha == 0.0:
+            break
+        Vs.append(v)
+        alphas.append(alpha)
+        u, beta = _normalise(A(v) - alpha * u)
+        Us.append(u)
+        betas.append(beta)
+        if beta == 0.0:
+            break
+        v, alpha = _normalise(AT(u) - beta * v)
+    kk = len(Vs)
+    B = np.zeros((kk + 1, kk))
+    for i in range(kk):
+        B[i, i] = alphas[i]
+        B[i + 1, i] = betas[i]
+    return Us, Vs, B, beta1
+
+
+def hybrid_lsqr(A, AT, b, n_iter, lam):
+    """x_k = V_k y_k, y_k = argmin ||beta1 e1 - B_k y||^2 + lam^2 ||y||^2.
+
+    The projected problem is solved at every k by dense FP64 least squares on
+    [B_k; lam I].  hist: 'res' = ||[beta1 e1; 0] - [B_k; lam I] y_k|| (the
+    residual of the projected Tikhonov problem, equal to the augmented-system
+    residual because U_{k+1} has orthonormal columns), 'y' = the last y_k.
+    """
+    Us, Vs, B, beta1 = golub_kahan(A, AT, b, n_iter)
+    hist = {"res": []}
+    y = np.zeros(0)
+    for k in range(1, B.shape[1] + 1):
+        Bk = B[: k + 1, :k]
+        M = np.vstack([Bk, lam * np.eye(k)])
+        rhs = np.zeros(2 * k + 1)
+        rhs[0] = beta1
+        y, *_ = np.linalg.lstsq(M, rhs, rcond=None)
+        hist["res"].append(float(np.linalg.norm(M @ y - rhs)))
+    x = np.zeros_like(Vs[0]) if Vs else np.zeros_like(AT(np.asarray(b, dtype=np.float64)))
+    for i, yi in enumerate(y):
+        x = x + yi * Vs[i]
+    hist["y"] = y
+    hist["res"] = np.asarray(hist["res"])
+    return x, hist
+
+
+# --------------------------------------------------------------------------
+# Isotropic TV and its IRN majorants (Sec. 2.3).
+# --------------------------------------------------------------------------
+def grad(x):
+    """D x: forward differences along x, y, z (unit spacing, Neumann).
+
+    ``x`` has shape (nz, ny, nx); returns shape (3, nz, ny, nx) with the x,
+    y, z components; the difference at the last index of each axis is 0.
+    """
+    g = np.zeros((3,) + x.shape)
+    g[0, :, :, :-1] = x[:, :, 1:] - x[:, :, :-1]
+    g[1, :, :-1, :] = x[:, 1:, :] - x[:, :-1, :]
+    g[2, :-1, :, :] = x[1:, :, :] - x[:-1, :, :]
+    return g
+
+
+def grad_T(g):
+    """D^T g, the exact adjoint of ``grad``."""
+    out = np.zeros(g.shape[1:])
+    gx, gy, gz = g[0], g[1], g[2]
+    out[:, :, :-1] -= gx[:, :, :-1]
+    out[:, :, 1:] += gx[:, :, :-1]
+    out[:, :-1, :] -= gy[:, :-1, :]
+    out[:, 1:, :] += gy[:, :-1, :]
+    out[:-1, :, :] -= gz[:-1, :, :]
+    out[1:, :, :] += gz[:-1, :, :]
+    return out
+
+
+def tv(x):
+    """Isotropic TV (eq. (TV)): sum over voxels of the gradient's 2-norm."""
+    g = grad(x)
+    return float(np.sum(np.sqrt(np.sum(g * g, axis=0))))
+
+
+def irn_weights(x, eps):
+    """IRN weights L = diag(w^{-1/2}) with w_i = sqrt(||(D x)_i||^2 + eps^2).
+
+    Returned as the per-voxel factor w^{-1/2} (shape (nz, ny, nx)); the same
+    factor multiplies all three gradient components of a voxel.
+    """
+    g = grad(x)
+    w = np.sqrt(np.sum(g * g, axis=0) + eps * eps)
+    return 1.0 / np.sqrt(w)
+
+
+def irn_tv_cgls(A, AT, b, shape, n_outer, n_inner, lam, eps):
+    """IRN-TV with inner CGLS (Sec. 2.3.1).
+
+    Outer iteration 0 uses L = I; outer iteration k >= 1 uses the weights of
+    the previous outer iterate.  Each outer iteration runs ``n_inner`` CGLS
+    steps on K = [A; lam L D] with right-hand side [b; 0], restarted from the
+    current iterate (a new Krylov space each time).  hist: 'res' = data
+    residual ||b - A x|| after every inner step, 'tv' after each outer step.
+    """
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros(shape)
+    hist = {"res": [], "tv": []}
+    for k in range(n_outer):
+        Lw = np.ones(shape) if k == 0 else irn_weights(x, eps)
+
+        def K(z, Lw=Lw):
+            return (A(z), lam * Lw[None] * grad(z))
+
+        def KT(r, Lw=Lw):
+            r1, r2 = r
+            return AT(r1) + lam * grad_T(Lw[None] * r2)
+
+        # CGLS on the stacked system, with stacked residual (r1, r2).
+        q1, q2 = K(x)
+        r1, r2 = b - q1, -q2
+        s = KT((r1, r2))
+        p = s.copy()
+        gamma = _dot(s, s)
+        for _ in range(n_inner):
+            if gamma == 0.0:
+                break
+            q1, q2 = K(p)
+            delta = _dot(q1, q1) + _dot(q2, q2)
+            alpha = gamma / delta
+            x = x + alpha * p
+            r1 = r1 - alpha * q1
+            r2 = r2 - alpha * q2
+            s = KT((r1, r2))
+            gamma_new = _dot(s, s)
+            beta = gamma_new / gamma
+            gamma = gamma_new
+            p = s + beta * p
+            hist["res"].append(_nrm(r1))
+        hist["tv"].append(tv(x))
+    return x, {k: np.asarray(v) for k, v in hist.items()}

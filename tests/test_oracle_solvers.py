@@ -1,0 +1,177 @@
+"""Pins of the oracle's FP64 Krylov solvers to things other than themselves.
+
+  * Krylov-subspace optimality, the definition the paper gives for each
+    method: CGLS/LSQR minimise ||A x - b|| (Sec. 2.1.1, eq.
+    (lest_squares_projected); Sec. 2.1.2, eq. (proj_LSQR)) and LSMR minimises
+    ||A^T r|| (Sec. 2.1.3, eq. (proj_LSMR)) over K_k(A^T A, A^T b), checked
+    against an explicitly built and twice-orthonormalised Krylov basis;
+  * SciPy's independent LSQR and LSMR (damped and undamped), iterate by iterate;
+  * dense least squares and damped normal equations at convergence
+    (Sec. 2.2, eqs. (Tikhonov) and (Tikhonov_augmented));
+  * CGLS == LSQR iterates (Sec. 2.1.2) and hybrid(lambda) == damped LSQR
+    (Sec. 2.2.1) in exact arithmetic;
+  * monotone residuals (Sec. 2.1.1: ||r_k|| decreases; LSMR: ||A^T r_k||);
+  * the recurred norms equal explicitly computed ones;
+  * breakdown with b = 0 or A^T b = 0 returns zero without NaN.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.sparse.linalg import lsmr as scipy_lsmr
+from scipy.sparse.linalg import lsqr as scipy_lsqr
+
+import oracle
+import synth
+from oracle import dense
+from oracle import solvers as S
+
+
+def _ct_problem(seed=0):
+    """A tiny cone-beam problem with its dense A (well inside brute-force size)."""
+    g = oracle.Geometry(nx=6, ny=6, nz=4, vx=1.0, vy=1.0, vz=1.0, nu=10, nv=6, du=1.0, dv=1.0,
+                        dso=20.0, dsd=32.0, angles=tuple(synth.angles(8, start=0.2)))
+    A = dense.system_matrix(g)
+    xt = synth.random_volume(g.vol_shape, seed).astype(np.float64).ravel()
+    b = A @ xt + 0.01 * np.random.default_rng(seed).standard_normal(A.shape[0])
+    return A, b
+
+
+def _random_problem(m=50, n=20, cond=30.0, seed=0):
+    rng = np.random.default_rng(seed)
+    U, _ = np.linalg.qr(rng.standard_normal((m, n)))
+    V, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    s = np.logspace(0, -math.log10(cond), n)
+    return (U * s) @ V.T, rng.standard_normal(m)
+
+
+def _ops(A):
+    return (lambda x: A @ x), (lambda y: A.T @ y)
+
+
+def _krylov_basis(A, b, k):
+    K = [A.T @ b]
+    for _ in range(k - 1):
+        K.append(A.T @ (A @ K[-1]))
+    K = np.array(K).T
+    K = K / np.linalg.norm(K, axis=0)
+    Q, _ = np.linalg.qr(K)
+    Q, _ = np.linalg.qr(Q)  # second pass for orthogonality
+    return Q
+
+
+@pytest.mark.parametrize("k", [1, 2, 4, 6])
+def test_krylov_optimality(k):
+    A, b = _random_problem(cond=10.0, seed=k)
+    Af, ATf = _ops(A)
+    V = _krylov_basis(A, b, k)
+    y_ls, *_ = np.linalg.lstsq(A @ V, b, rcond=None)
+    x_ls = V @ y_ls
+    # LSMR: minimise ||A^T (b - A V y)|| = || A^T b - (A^T A V) y ||.
+    y_mr, *_ = np.linalg.lstsq(A.T @ (A @ V), A.T @ b, rcond=None)
+    x_mr = V @ y_mr
+    for fn, want in ((S.cgls, x_ls), (S.lsqr, x_ls), (S.lsmr, x_mr)):
+        x, _ = fn(Af, ATf, b, k)
+        assert np.linalg.norm(x - want) <= 1e-9 * np.linalg.norm(want), fn.__name__
+    # The two criteria really differ at this k (so a swap would be caught).
+    if k >= 2:
+        assert np.linalg.norm(x_ls - x_mr) > 1e-6 * np.linalg.norm(x_ls)
+
+
+@pytest.mark.parametrize("lam", [0.0, 0.7])
+def test_against_scipy(lam):
+    for prob in (_random_problem(cond=50.0, seed=3), _ct_problem(1)):
+        A, b = prob
+        Af, ATf = _ops(A)
+        for k in (1, 3, 6, 8):
+            x, _ = S.lsqr(Af, ATf, b, k, lam)
+            xs = scipy_lsqr(A, b, damp=lam, atol=0, btol=0, conlim=0, iter_lim=k)[0]
+            assert np.linalg.norm(x - xs) <= 1e-9 * np.linalg.norm(xs)
+            x, _ = S.lsmr(Af, ATf, b, k, lam)
+            xs = scipy_lsmr(A, b, damp=lam, atol=0, btol=0, conlim=0, maxiter=k)[0]
+            assert np.linalg.norm(x - xs) <= 1e-9 * np.linalg.norm(xs)
+
+
+def test_converge_to_least_squares():
+    A, b = _random_problem(m=40, n=12, cond=5.0, seed=7)
+    Af, ATf = _ops(A)
+    x_ls, *_ = np.linalg.lstsq(A, b, rcond=None)
+    for fn in (S.cgls, S.lsqr, S.lsmr):
+        x, _ = fn(Af, ATf, b, 40)
+        assert np.linalg.norm(x - x_ls) <= 1e-10 * np.linalg.norm(x_ls), fn.__name__
+
+
+@pytest.mark.parametrize("lam", [0.3, 2.0])
+def test_damped_normal_equations(lam):
+    A, b = _ct_problem(2)
+    Af, ATf = _ops(A)
+    n = A.shape[1]
+    x_t = np.linalg.solve(A.T @ A + lam * lam * np.eye(n), A.T @ b)
+    for fn in (S.cgls, S.lsqr, S.lsmr):
+        # Converged well inside 100 steps (cond(A^T A + lam^2 I) <= 1e2); run
+        # much longer, plain CGLS's recurred residual drifts from b - A x.
+        x, _ = fn(Af, ATf, b, 100, lam)
+        assert np.linalg.norm(x - x_t) <= 1e-8 * np.linalg.norm(x_t), fn.__name__
+    x, _ = S.hybrid_lsqr(Af, ATf, b, 100, lam)
+    assert np.linalg.norm(x - x_t) <= 1e-8 * np.linalg.norm(x_t)
+
+
+def test_cgls_equals_lsqr_and_hybrid_equals_damped():
+    A, b = _ct_problem(3)
+    Af, ATf = _ops(A)
+    for k in (1, 5, 10):
+        xc, _ = S.cgls(Af, ATf, b, k)
+        xq, _ = S.lsqr(Af, ATf, b, k)
+        assert np.linalg.norm(xc - xq) <= 1e-9 * np.linalg.norm(xq)
+        for lam in (0.5, 3.0):
+            xd, _ = S.lsqr(Af, ATf, b, k, lam)
+            xh, _ = S.hybrid_lsqr(Af, ATf, b, k, lam)
+            xcd, _ = S.cgls(Af, ATf, b, k, lam)
+            assert np.linalg.norm(xh - xd) <= 1e-10 * np.linalg.norm(xd)
+            assert np.linalg.norm(xcd - xd) <= 1e-9 * np.linalg.norm(xd)
+
+
+def test_monotone_and_recurred_norms():
+    A, b = _ct_problem(4)
+    Af, ATf = _ops(A)
+    n = 15
+    res_c, res_q, nrm_m = [], [], []
+    for k in range(1, n + 1):
+        xc, hc = S.cgls(Af, ATf, b, k)
+        xq, hq = S.lsqr(Af, ATf, b, k)
+        xm, hm = S.lsmr(Af, ATf, b, k)
+        rc, rq = np.linalg.norm(b - A @ xc), np.linalg.norm(b - A @ xq)
+        rm = np.linalg.norm(A.T @ (b - A @ xm))
+        assert abs(hc["res"][-1] - rc) <= 1e-9 * rc
+        assert abs(hq["res"][-1] - rq) <= 1e-9 * rq
+        assert abs(hm["normal"][-1] - rm) <= 1e-7 * rm
+        res_c.append(rc), res_q.append(rq), nrm_m.append(rm)
+    assert np.all(np.diff(res_c) <= 1e-12 * res_c[0])
+    assert np.all(np.diff(res_q) <= 1e-12 * res_q[0])
+    assert np.all(np.diff(nrm_m) <= 1e-12 * nrm_m[0])
+    # Damped recurrences against explicit augmented norms.
+    lam = 0.8
+    xq, hq = S.lsqr(Af, ATf, b, 7, lam)
+    aug = math.sqrt(np.linalg.norm(b - A @ xq) ** 2 + lam * lam * np.linalg.norm(xq) ** 2)
+    assert abs(hq["res"][-1] - aug) <= 1e-9 * aug
+    xm, hm = S.lsmr(Af, ATf, b, 7, lam)
+    nrm = np.linalg.norm(A.T @ (b - A @ xm) - lam * lam * xm)
+    assert abs(hm["normal"][-1] - nrm) <= 1e-7 * nrm
+    xh, hh = S.hybrid_lsqr(Af, ATf, b, 7, lam)
+    assert abs(hh["res"][-1] - aug) <= 1e-9 * aug
+
+
+def test_breakdown_returns_zero():
+    A, b = _ct_problem(5)
+    Af, ATf = _ops(A)
+    zero = np.zeros_like(b)
+    for fn in (S.cgls, S.lsqr, S.lsmr):
+        x, _ = fn(Af, ATf, zero, 5)
+        assert np.all(x == 0.0) and np.all(np.isfinite(x))
+    # b orthogonal to range(A): A^T b = 0, alpha_1 = 0.
+    Q, _ = np.linalg.qr(np.hstack([A, np.random.default_rng(0).standard_normal((A.shape[0], 1))]))
+    bn = Q[:, -1] * (np.linalg.norm(A.T @ Q[:, -1]) < 1e-9)
+    if np.linalg.norm(bn) > 0:
+        for fn in (S.cgls, S.lsqr, S.lsmr):
+            x, _ = fn(Af, ATf, bn, 5)
+            assert np.all(np.isfinite(x)) and np.linalg.norm(x) < 1e-6
