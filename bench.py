@@ -1,0 +1,243 @@
+#!/usr/bin/env python3
+"""Benchmark of the Krylov CBCT hot path on one MI355X.
+
+Workload "medical256": 256^3 volume at 0.5 mm (40 seeded ellipsoids),
+512 x 512 detector at 0.4 mm, 360 angles over 360 deg, DSO 1000 mm,
+DSD 1500 mm, Poisson noise at I0 = 1e5 (synthetic stand-in for the medical
+scan of the paper's Sec. 3.2).  All inputs are resident in HBM before any
+timed region starts.
+
+A step is one CGLS iteration: forward projection, matched back projection,
+the fused vector updates and reductions, and the FP64 scalar recurrences.
+`value` is CGLS iterations per second.  The same JSON line also reports the
+forward projector in GRays/s, the back projector in GVoxel-views/s, LSQR
+and LSMR iterations per second, 30-iteration solve times, a roofline entry
+for the dominant kernel and the CPU oracle's rate on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GRays/s fwd proj, GVoxel-views/s backproj; CGLS it/s; p50/p99 recon latency"
+WORKLOAD = "medical256"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def src_digest(*names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2211_14212_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def timed(fn, reps, torch):
+    """Average ms per call, HIP events on the current stream (where the kernels run)."""
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    e0.record(st)
+    for _ in range(reps):
+        fn()
+    e1.record(st)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def iter_rate(plan, b, solver, warmup, steps, torch):
+    """Iterations/s of `solver` over `steps` iterations after `warmup` ones."""
+    st = plan.state(b, solver, warmup + steps)
+    st.step(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st.stream)
+    for _ in range(steps):
+        st.step(1)
+    e1.record(st.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    hist = st.history.cpu().numpy()
+    st.close()
+    return steps / (ms / 1000.0), ms, hist
+
+
+def cpu_baseline(gd, x, n_angles_sample=24):
+    """The FP64 oracle on the host: forward and scatter adjoint over a subset
+    of the angles, scaled to one CGLS iteration of the full workload."""
+    import numpy as np
+
+    import oracle
+
+    g = oracle.Geometry.from_dict(gd)
+    na = len(g.angles)
+    sel = np.linspace(0, na, n_angles_sample, endpoint=False).astype(int)
+    gs = g.with_angles([g.angles[a] for a in sel])
+    t0 = time.perf_counter()
+    y = oracle.forward(gs, x)
+    t1 = time.perf_counter()
+    oracle.adjoint(gs, y)
+    t2 = time.perf_counter()
+    scale = na / n_angles_sample
+    t_iter = (t2 - t0) * scale
+    return {
+        "value": 1.0 / t_iter, "unit": "CGLS it/s", "cores": oracle.num_threads(), "kind": "oracle",
+        "sample": (f"FP64 Siddon forward + scatter adjoint of the {WORKLOAD} phantom over {n_angles_sample} of "
+                   f"{na} angles ({t2 - t0:.1f} s), scaled x{scale:.0f} to one CGLS iteration; vector updates "
+                   "(<1% of an iteration) not included"),
+        "fwd_grays_per_s": (len(gs.angles) * g.nu * g.nv) / (t1 - t0) / 1e9,
+        "bwd_gvoxel_views_per_s": (g.nx * g.ny * g.nz * len(gs.angles)) / (t2 - t1) / 1e9,
+        "cpu_model": _cpu_model(),
+    }
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def traffic_entry(kernel_key, digest, launches_bytes_alg):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, if they
+    were taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"{WORKLOAD}_counters.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    k = d.get("kernels", {}).get(kernel_key)
+    if not k or d.get("src_digest") != digest:
+        return None
+    return k.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--reps", type=int, default=5, help="calls per projector timing")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-solves", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU angle-sharded "
+              "path is a design in DESIGN.md, not built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2211_14212_amd as kct
+    import synth
+
+    kct.require_gpu()
+    dev = torch.device("cuda", 0)
+    gd = synth.geometry(WORKLOAD)
+    kg = kct.Geometry.from_dict(gd)
+    stats = json.load(open(os.path.join(ROOT, "tests", "golden", "workload_stats.json")))[WORKLOAD]
+
+    log("[bench] phantom")
+    x_true = synth.phantom(WORKLOAD)
+    plan = kct.Plan(kg)
+    xt = torch.from_numpy(x_true).to(dev)
+    log("[bench] clean projections (GPU forward) + Poisson noise")
+    b_clean = plan.forward(xt).cpu().numpy()
+    b_np, noise_info = synth.add_noise(b_clean, synth.WORKLOADS[WORKLOAD]["noise"], synth.WORKLOADS[WORKLOAD]["seed"])
+    del b_clean
+    b = torch.from_numpy(b_np).to(dev)
+    torch.cuda.synchronize()
+
+    # ---- the step: one CGLS iteration ------------------------------------
+    log("[bench] CGLS iterations")
+    cgls_rate, cgls_ms, _ = iter_rate(plan, b, "cgls", args.warmup, args.steps, torch)
+    log(f"[bench] CGLS {cgls_rate:.2f} it/s")
+
+    # ---- operators ---------------------------------------------------------
+    log("[bench] projector timings")
+    y_out = torch.empty(kg.proj_shape, device=dev)
+    x_out = torch.empty(kg.vol_shape, device=dev)
+    fwd_ms = timed(lambda: plan.forward(xt, out=y_out), args.reps, torch)
+    bwd_ms = timed(lambda: plan.backproject(b, out=x_out), args.reps, torch)
+    n_rays, n_vv, nnz = stats["rays"], stats["voxel_views"], stats["nnz"]
+    M, N = stats["voxels"], stats["rays"]
+    log(f"[bench] fwd {fwd_ms:.2f} ms  bwd {bwd_ms:.2f} ms")
+
+    lsqr_rate, _, _ = iter_rate(plan, b, "lsqr", args.warmup, args.steps, torch)
+    lsmr_rate, _, _ = iter_rate(plan, b, "lsmr", args.warmup, args.steps, torch)
+    log(f"[bench] LSQR {lsqr_rate:.2f} it/s  LSMR {lsmr_rate:.2f} it/s")
+
+    solves = {}
+    if not args.no_solves:
+        for solver in ("cgls", "lsqr", "lsmr"):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            xs, hs = plan.solve(b, solver, 30)
+            torch.cuda.synchronize()
+            solves[f"{solver}30_s"] = round(time.perf_counter() - t0, 4)
+            h = hs.cpu().numpy()
+            solves[f"{solver}30_last_res"] = float(h[-1, 0])
+            err = float(torch.linalg.vector_norm(xs - xt) / torch.linalg.vector_norm(xt))
+            solves[f"{solver}30_rel_err_vs_phantom"] = round(err, 4)
+        log(f"[bench] solves {solves}")
+
+    # ---- roofline of the dominant kernel ----------------------------------
+    # Algorithmic bytes of a matrix-free sparse matvec: every nonzero a_ij
+    # reads one input value, every output is written once (FP32).
+    if fwd_ms >= bwd_ms:
+        kname, ms, alg = "forward", fwd_ms, nnz * 4 + N * 4
+        digest = src_digest("proj_fwd.hip")
+    else:
+        kname, ms, alg = "backward", bwd_ms, nnz * 4 + M * 4
+        digest = src_digest("proj_bwd.hip")
+    achieved = alg / (ms / 1000.0) / 1e9
+    traffic = traffic_entry(kname, digest, alg)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
+                "launch_ms": round(ms, 3), "algorithmic_bytes_per_launch": alg}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        cpu = cpu_baseline(gd, x_true)
+        log(f"[bench] cpu {cpu['value']:.4f} it/s on {cpu['cores']} threads")
+
+    out = {
+        "metric": METRIC, "value": round(cgls_rate, 3), "unit": "CGLS it/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(cgls_ms / args.steps, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": WORKLOAD, "volume": [gd["nx"], gd["ny"], gd["nz"]], "voxel_mm": gd["vx"],
+                   "detector": [gd["nu"], gd["nv"]], "pixel_mm": gd["du"], "angles": len(gd["angles"]),
+                   "dso_mm": gd["dso"], "dsd_mm": gd["dsd"], "solver": "cgls", "phantom": "40 seeded ellipsoids",
+                   "noise": "Poisson I0=1e5", "poisson_clamped_fraction": round(noise_info["clamped_fraction"], 5)},
+        "fwd_grays_per_s": round(n_rays / (fwd_ms / 1000.0) / 1e9, 3),
+        "fwd_hit_grays_per_s": round(stats["hit_rays"] / (fwd_ms / 1000.0) / 1e9, 3),
+        "bwd_gvoxel_views_per_s": round(n_vv / (bwd_ms / 1000.0) / 1e9, 3),
+        "fwd_ms": round(fwd_ms, 3), "bwd_ms": round(bwd_ms, 3),
+        "segments_per_s": round(nnz / (fwd_ms / 1000.0) / 1e9, 2),
+        "lsqr_it_per_s": round(lsqr_rate, 3), "lsmr_it_per_s": round(lsmr_rate, 3),
+        "solves": solves, "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,215 @@
+/*
+ * kct.h -- C ABI of the Krylov cone-beam CT library for MI355X (gfx950).
+ *
+ * The library solves the CBCT problem A x + e = b (paper Sec. 1, eq.
+ * (original_pbm)) with the Krylov methods of Sec. 2 using only products with
+ * the matched pair A (cone-beam forward projection) and A^T (its exact
+ * transpose), both hand-written HIP kernels.
+ *
+ * System matrix.  Row i is the ray from the source to the centre of detector
+ * pixel i; column j is voxel j; a_ij is the length in mm of ray i inside
+ * voxel j (Siddon's radiological path; the paper leaves the discretisation to
+ * its toolbox).  A is never stored.
+ *
+ * Geometry (the paper gives none; the convention is fixed here):
+ *   voxel (i,j,k) = half-open box [X0+i vx, X0+(i+1) vx) x [Y0+j vy, ...) x
+ *                   [Z0+k vz, ...), X0 = ox - nx vx/2 (same for y, z);
+ *   source        s = (DSO cos t, DSO sin t, 0) for gantry angle t;
+ *   detector      centre s + DSD (-cos t, -sin t, 0), axes
+ *                 e_u = (-sin t, cos t, 0) and e_v = (0, 0, 1);
+ *   pixel (iu,iv) centre = centre + (iu-(nu-1)/2) du e_u + (iv-(nv-1)/2) dv e_v.
+ * Lengths are in mm, angles in radians, attenuation in 1/mm.
+ *
+ * Layouts.  Volumes are contiguous [nz][ny][nx] (x fastest); projections are
+ * contiguous [n_angles][nv][nu] (u fastest).
+ *
+ * Ownership.  The caller allocates and owns every device buffer passed in
+ * (volumes, projections, right-hand side, solution, workspace, history).  A
+ * plan owns its geometry tables and the padded volume copies the forward
+ * projector reads; kct_plan_device_bytes reports that memory.  The library
+ * never frees caller memory.
+ *
+ * Streams.  Every call that takes a `stream` (a hipStream_t, or NULL for the
+ * null stream) only enqueues work on it and returns; the caller synchronises.
+ * Calls on one plan must not overlap in time unless they use different plans.
+ *
+ * Errors.  Argument and geometry checks happen before anything is enqueued and
+ * return a status; kct_last_error() then holds a message for the calling
+ * thread.  No C++ exception crosses this interface and the library never
+ * aborts.  A launch failure returns KCT_E_DEVICE.  Krylov breakdown (a zero
+ * norm, e.g. b = 0) is not an error: the remaining iterations leave x
+ * unchanged and report it in the history.
+ */
+#ifndef KCT_H
+#define KCT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum kct_status {
+    KCT_OK = 0,
+    KCT_E_INVALID_ARG = 1, /* null pointer, bad size or unknown enum value          */
+    KCT_E_GEOMETRY = 2,    /* geometry that the convention above cannot represent   */
+    KCT_E_DTYPE = 3,       /* storage type not supported for this call              */
+    KCT_E_OOM = 4,         /* device allocation by the library failed               */
+    KCT_E_BUDGET = 5,      /* a caller-provided buffer is too small                 */
+    KCT_E_DEVICE = 6,      /* a HIP call or kernel launch failed                    */
+    KCT_E_NONFINITE = 7,   /* the solver met a NaN or Inf (e.g. in b)               */
+    KCT_E_STATE = 8        /* call made on a state in the wrong phase               */
+} kct_status;
+
+/* Storage types of device vectors.  Arithmetic is FP32 for ray and voxel
+ * accumulation and FP64 for the Krylov scalars, whatever the storage type. */
+typedef enum kct_dtype {
+    KCT_F32 = 0,
+    KCT_BF16 = 1, /* bfloat16, round-to-nearest-even on store */
+    KCT_F16 = 2   /* IEEE binary16, round-to-nearest-even on store */
+} kct_dtype;
+
+/* Circular cone-beam geometry (see the convention at the top of this file). */
+typedef struct kct_geometry {
+    int32_t nx, ny, nz;    /* voxels per axis, > 0                                   */
+    double vx, vy, vz;     /* voxel size (mm), > 0                                    */
+    double ox, oy, oz;     /* volume centre offset from the rotation axis (mm)        */
+    int32_t nu, nv;        /* detector pixels along e_u and e_v, > 0                  */
+    double du, dv;         /* pixel pitch (mm), > 0                                   */
+    double dso, dsd;       /* source-origin and source-detector distances (mm)        */
+    int32_t n_angles;      /* number of gantry angles, > 0                            */
+    const double *angles;  /* host pointer to n_angles radians; copied by the plan    */
+} kct_geometry;
+
+typedef struct kct_plan kct_plan;
+
+/*
+ * Create a plan for `geom` on HIP device `device`: validates the geometry
+ * (DSO > 0, DSD > DSO, and the volume's bounding cylinder strictly between
+ * the source orbit and the detector plane), builds the per-angle FP64 tables
+ * on the host (cos/sin evaluated once, in double precision) and copies them
+ * to the device.  Returns KCT_E_GEOMETRY for a geometry outside the
+ * convention.  `*out` receives the plan, owned by the caller until
+ * kct_plan_destroy.
+ */
+kct_status kct_plan_create(const kct_geometry *geom, int device, kct_plan **out);
+
+/* Free a plan and every device buffer it owns.  NULL is accepted. */
+kct_status kct_plan_destroy(kct_plan *plan);
+
+/* Device bytes the plan holds now (tables and padded volume copies). */
+kct_status kct_plan_device_bytes(const kct_plan *plan, size_t *bytes);
+
+/*
+ * Forward projection (paper Sec. 2: every Krylov iteration applies A once):
+ * d_proj = A d_vol.  d_vol: [nz][ny][nx] of `vol_dtype`; d_proj:
+ * [n_angles][nv][nu] of `proj_dtype`, overwritten.  Ray sums accumulate in
+ * FP32; ray geometry is evaluated in FP64.  Enqueued on `stream`.
+ */
+kct_status kct_forward(kct_plan *plan, const void *d_vol, int32_t vol_dtype, void *d_proj,
+                       int32_t proj_dtype, void *stream);
+
+/*
+ * Back projection with the exact transpose of kct_forward (paper Sec. 2.1.4
+ * and Sec. 4: a mismatched back projector degrades the Krylov methods):
+ * d_vol = A^T d_proj.  Voxel-driven gather; FP32 accumulation.  Layouts as in
+ * kct_forward; d_vol is overwritten.  Enqueued on `stream`.
+ */
+kct_status kct_backproject(kct_plan *plan, const void *d_proj, int32_t proj_dtype, void *d_vol,
+                           int32_t vol_dtype, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Solvers                                                                   */
+/* ------------------------------------------------------------------------ */
+
+typedef enum kct_solver {
+    KCT_CGLS = 0,        /* Sec. 2.1.1; damped by lambda (Sec. 2.2, augmented system) */
+    KCT_LSQR = 1,        /* Sec. 2.1.2; damped by lambda                              */
+    KCT_LSMR = 2,        /* Sec. 2.1.3; damped by lambda                              */
+    KCT_HYBRID_LSQR = 3, /* Sec. 2.2.1 with a fixed lambda; stores the basis V_k      */
+    KCT_IRN_TV_CGLS = 4  /* Sec. 2.3.1: IRN majorants of isotropic TV, inner CGLS     */
+} kct_solver;
+
+/* Columns of one history row (FP64), one row per iteration (for IRN-TV: per
+ * inner iteration).
+ *   [0] residual norm the method recurs: CGLS ||b - A x_k||, LSQR and hybrid
+ *       ||[b;0] - [A; lam I] x_k||, LSMR ||[A; lam I]^T r_k||, IRN-TV ||b - A x||;
+ *   [1] alpha_k; [2] beta_k (the method's own two leading scalars);
+ *   [3] 1 if the method had broken down (zero norm) by this iteration, else 0. */
+#define KCT_HIST_COLS 4
+
+typedef struct kct_solve_params {
+    int32_t solver;    /* kct_solver                                            */
+    int32_t n_iter;    /* iterations (IRN-TV: ignored, tv_outer*tv_inner used)   */
+    double lambda;     /* Tikhonov damping (CGLS/LSQR/LSMR/hybrid) or TV weight  */
+    int32_t tv_outer;  /* IRN-TV outer iterations                               */
+    int32_t tv_inner;  /* IRN-TV inner CGLS iterations per outer iteration       */
+    double tv_eps;     /* IRN-TV smoothing epsilon of the weights                */
+    int32_t vec_dtype; /* storage of the vectors the projectors read and write:
+                          KCT_F32, KCT_BF16 or KCT_F16; x is always FP32       */
+    int32_t reserved;
+} kct_solve_params;
+
+/* Workspace bytes kct_solve needs for `params` on `plan`. */
+kct_status kct_solve_workspace_bytes(const kct_plan *plan, const kct_solve_params *params,
+                                     size_t *bytes);
+
+/*
+ * Run a solver from x0 = 0 for a fixed number of iterations (the paper's
+ * iterates live in K_k(A^T A, A^T b), Sec. 2).  d_b: FP32 projections
+ * [n_angles][nv][nu]; d_x: FP32 volume [nz][ny][nx], overwritten with x_k.
+ * d_ws: device workspace of at least kct_solve_workspace_bytes (contents
+ * undefined on entry and exit).  d_history: device FP64 array of
+ * n_rows * KCT_HIST_COLS, n_rows = n_iter (IRN-TV: tv_outer * tv_inner), or
+ * NULL.  All Krylov scalars stay in device FP64 memory; nothing synchronises
+ * the host inside the loop.  Enqueued on `stream`.
+ */
+kct_status kct_solve(kct_plan *plan, const kct_solve_params *params, const void *d_b, void *d_x,
+                     void *d_ws, size_t ws_bytes, double *d_history, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Iteration-level API (continuous-batching server, checkpoint tests)        */
+/* ------------------------------------------------------------------------ */
+
+typedef struct kct_state kct_state;
+
+/*
+ * Bind a solver run to caller buffers without running it: d_b, d_x, d_ws and
+ * d_history as for kct_solve (they must stay valid until kct_state_destroy).
+ * The state remembers `stream`; kct_state_step enqueues its work there.
+ */
+kct_status kct_state_create(kct_plan *plan, const kct_solve_params *params, const void *d_b, void *d_x,
+                            void *d_ws, size_t ws_bytes, double *d_history, void *stream,
+                            kct_state **out);
+
+/* Enqueue up to `n_steps` more iterations (the first call also enqueues the
+ * initialisation).  Returns at once; the host counts iterations enqueued, so
+ * no device synchronisation is needed. */
+kct_status kct_state_step(kct_state *state, int32_t n_steps);
+
+/* Iterations enqueued so far and whether all requested iterations are. */
+kct_status kct_state_progress(const kct_state *state, int32_t *iters_enqueued, int32_t *finished);
+
+/* Release a state (not the caller's buffers).  NULL is accepted. */
+kct_status kct_state_destroy(kct_state *state);
+
+/* ------------------------------------------------------------------------ */
+/* Diagnostics                                                               */
+/* ------------------------------------------------------------------------ */
+
+/* Static English name of a status. */
+const char *kct_status_str(kct_status status);
+
+/* Detail of the last failed call on this thread ("" if none); valid until
+ * the next call on this thread. */
+const char *kct_last_error(void);
+
+/* Library version string. */
+const char *kct_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KCT_H */

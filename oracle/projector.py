@@ -109,6 +109,7 @@ def _load():
                                              P(ctypes.c_int64), P(ctypes.c_double), ctypes.c_int]
             lib.ora_forward_rays.argtypes = [P(_CGeom), P(ctypes.c_double), P(ctypes.c_int64),
                                              ctypes.c_int64, P(ctypes.c_double)]
+            lib.ora_count_nnz.argtypes = [P(_CGeom), P(ctypes.c_int64), P(ctypes.c_int64)]
             lib.ora_num_threads.restype = ctypes.c_int
             _lib = lib
     return _lib
@@ -174,6 +175,16 @@ def ray_segments(g: Geometry, a: int, iv: int, iu: int):
     if n < 0:
         raise RuntimeError("oracle ray_segments failed")
     return idx[:n].copy(), ln[:n].copy()
+
+
+def count_nnz(g: Geometry):
+    """(nonzero entries of A, rays that meet the volume) for geometry g."""
+    lib = _load()
+    nnz, hits = ctypes.c_int64(), ctypes.c_int64()
+    cg, _keep = _cgeom(g)
+    if lib.ora_count_nnz(ctypes.byref(cg), ctypes.byref(nnz), ctypes.byref(hits)) != 0:
+        raise MemoryError("oracle count_nnz: allocation failed")
+    return int(nnz.value), int(hits.value)
 
 
 def num_threads() -> int:

@@ -287,6 +287,35 @@ int ora_forward_rays(const ora_geom *g, const double *x, const int64_t *rays, in
     return err;
 }
 
+/* Number of nonzero entries of A (segments of positive length), summed over
+ * every ray: the count the algorithmic-traffic model of a sparse matvec uses.
+ * Also returns the number of rays with at least one segment. */
+int ora_count_nnz(const ora_geom *g, int64_t *nnz, int64_t *hit_rays)
+{
+    int64_t nray = (int64_t)g->na * g->nv * g->nu;
+    int64_t tot = 0, hits = 0;
+    int err = 0;
+#pragma omp parallel reduction(+ : tot, hits) reduction(| : err)
+    {
+        ora_scratch s;
+        if (!scratch_alloc(g, &s)) err = 1;
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t r = 0; r < nray; ++r) {
+            if (err) continue;
+            int iu = (int)(r % g->nu);
+            int iv = (int)((r / g->nu) % g->nv);
+            int a = (int)(r / ((int64_t)g->nu * g->nv));
+            int n = trace_ray(g, a, iv, iu, &s);
+            tot += n;
+            hits += n > 0;
+        }
+        scratch_free(&s);
+    }
+    *nnz = tot;
+    *hit_rays = hits;
+    return err;
+}
+
 int ora_num_threads(void)
 {
 #ifdef _OPENMP

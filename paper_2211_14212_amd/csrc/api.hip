@@ -1,0 +1,267 @@
+// Plan creation, geometry validation, errors and the plain projector calls.
+
+#include "kct_internal.hpp"
+
+#include <cmath>
+#include <cstring>
+#include <new>
+
+namespace kct {
+
+namespace {
+thread_local std::string g_last_error;
+
+// Makes the plan's device current for the duration of a call and restores
+// the caller's device afterwards.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+} // namespace
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+kct_status fail(kct_status s, const std::string &msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+kct_status check_hip(hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return KCT_OK;
+    return fail(e == hipErrorOutOfMemory ? KCT_E_OOM : KCT_E_DEVICE,
+                std::string(what) + ": " + hipGetErrorString(e));
+}
+
+size_t dtype_size(int dt) { return dt == KCT_F32 ? 4 : 2; }
+bool dtype_ok(int dt) { return dt == KCT_F32 || dt == KCT_BF16 || dt == KCT_F16; }
+
+static kct_status validate(const kct_geometry *g)
+{
+    if (!g) return fail(KCT_E_INVALID_ARG, "geometry is NULL");
+    if (g->nx <= 0 || g->ny <= 0 || g->nz <= 0) return fail(KCT_E_GEOMETRY, "volume size must be positive");
+    if (g->nu <= 0 || g->nv <= 0) return fail(KCT_E_GEOMETRY, "detector size must be positive");
+    if (g->n_angles <= 0) return fail(KCT_E_GEOMETRY, "n_angles must be positive");
+    if (!g->angles) return fail(KCT_E_INVALID_ARG, "angles is NULL");
+    if (!finite_pos(g->vx) || !finite_pos(g->vy) || !finite_pos(g->vz))
+        return fail(KCT_E_GEOMETRY, "voxel size must be positive and finite");
+    if (!finite_pos(g->du) || !finite_pos(g->dv)) return fail(KCT_E_GEOMETRY, "pixel pitch must be positive");
+    if (!std::isfinite(g->ox) || !std::isfinite(g->oy) || !std::isfinite(g->oz))
+        return fail(KCT_E_GEOMETRY, "volume offset must be finite");
+    if (!finite_pos(g->dso)) return fail(KCT_E_GEOMETRY, "DSO must be positive");
+    if (!(std::isfinite(g->dsd) && g->dsd > g->dso)) return fail(KCT_E_GEOMETRY, "DSD must exceed DSO");
+    for (int a = 0; a < g->n_angles; ++a)
+        if (!std::isfinite(g->angles[a])) return fail(KCT_E_GEOMETRY, "angles must be finite");
+    const double X0 = g->ox - 0.5 * g->nx * g->vx, Y0 = g->oy - 0.5 * g->ny * g->vy;
+    double R = 0.0;
+    for (double x : {X0, X0 + g->nx * g->vx})
+        for (double y : {Y0, Y0 + g->ny * g->vy}) R = std::max(R, std::sqrt(x * x + y * y));
+    if (R >= g->dso) return fail(KCT_E_GEOMETRY, "the volume reaches the source orbit (need radius < DSO)");
+    if (R >= g->dsd - g->dso) return fail(KCT_E_GEOMETRY, "the volume reaches the detector (need radius < DSD-DSO)");
+    const double nray = double(g->n_angles) * g->nu * g->nv;
+    if (nray > 4.0e12) return fail(KCT_E_GEOMETRY, "too many rays");
+    return KCT_OK;
+}
+
+static void build_tables(Plan &p)
+{
+    const kct_geometry &g = p.geom;
+    GeoParams &gp = p.gp;
+    gp.nx = g.nx; gp.ny = g.ny; gp.nz = g.nz; gp.nu = g.nu; gp.nv = g.nv; gp.na = g.n_angles;
+    gp.vx = g.vx; gp.vy = g.vy; gp.vz = g.vz; gp.du = g.du; gp.dv = g.dv;
+    gp.X0 = g.ox - 0.5 * g.nx * g.vx;
+    gp.Y0 = g.oy - 0.5 * g.ny * g.vy;
+    gp.Z0 = g.oz - 0.5 * g.nz * g.vz;
+    gp.cu = 0.5 * (g.nu - 1);
+    gp.cv = 0.5 * (g.nv - 1);
+    gp.dso = g.dso; gp.dsd = g.dsd;
+    gp.ivz = 1.0 / g.vz;
+    p.host_tab.resize(g.n_angles);
+    for (int a = 0; a < g.n_angles; ++a) {
+        const double cs = std::cos(p.angles[a]), sn = std::sin(p.angles[a]);
+        AngleGeo &A = p.host_tab[a];
+        A.cs = cs; A.sn = sn;
+        A.sx = g.dso * cs; A.sy = g.dso * sn;
+        A.svx = (A.sx - gp.X0) / g.vx;
+        A.svy = (A.sy - gp.Y0) / g.vy;
+        A.svz = (0.0 - gp.Z0) / g.vz;
+        A.d0x = -g.dsd * cs / g.vx;
+        A.d0y = -g.dsd * sn / g.vy;
+        A.eux = -sn / g.vx;
+        A.euy = cs / g.vy;
+        // Rays run mostly along x when |cos| >= |sin|; neighbouring pixels are
+        // then displaced along y, so the y-fastest copy keeps a wave coalesced.
+        A.transposed = std::fabs(cs) >= std::fabs(sn) ? 1 : 0;
+        A.pad = 0;
+    }
+    p.pad.px = g.nx + 2;
+    p.pad.py = g.ny + 2;
+    p.pad.pz = g.nz + 2;
+    p.pad.vox = p.pad.px * p.pad.py * p.pad.pz;
+}
+
+} // namespace kct
+
+using namespace kct;
+
+extern "C" {
+
+const char *kct_version(void) { return "kct 0.1 (gfx950)"; }
+
+const char *kct_last_error(void) { return g_last_error.c_str(); }
+
+const char *kct_status_str(kct_status s)
+{
+    switch (s) {
+    case KCT_OK: return "ok";
+    case KCT_E_INVALID_ARG: return "invalid argument";
+    case KCT_E_GEOMETRY: return "unsupported geometry";
+    case KCT_E_DTYPE: return "unsupported storage type";
+    case KCT_E_OOM: return "out of device memory";
+    case KCT_E_BUDGET: return "buffer too small";
+    case KCT_E_DEVICE: return "device error";
+    case KCT_E_NONFINITE: return "non-finite value";
+    case KCT_E_STATE: return "invalid state";
+    }
+    return "unknown status";
+}
+
+kct_status kct_plan_create(const kct_geometry *geom, int device, kct_plan **out)
+{
+    g_last_error.clear();
+    if (!out) return fail(KCT_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    kct_status s = validate(geom);
+    if (s != KCT_OK) return s;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return fail(KCT_E_DEVICE, "no such HIP device");
+    kct_plan *p = new (std::nothrow) kct_plan();
+    if (!p) return fail(KCT_E_OOM, "host allocation failed");
+    p->device = device;
+    p->geom = *geom;
+    p->angles.assign(geom->angles, geom->angles + geom->n_angles);
+    p->geom.angles = p->angles.data();
+    build_tables(*p);
+    s = choose_bwd_shape(*p);
+    if (s != KCT_OK) {
+        delete p;
+        return s;
+    }
+    DeviceGuard dg(device);
+    if (!dg.ok) {
+        delete p;
+        return fail(KCT_E_DEVICE, "hipSetDevice failed");
+    }
+    std::vector<double> invv(geom->nv);
+    for (int iv = 0; iv < geom->nv; ++iv) {
+        const double v = (iv - p->gp.cv) * geom->dv;
+        invv[iv] = v != 0.0 ? 1.0 / v : 0.0;
+    }
+    s = check_hip(hipMalloc(&p->d_tab, sizeof(AngleGeo) * geom->n_angles), "plan table allocation");
+    if (s == KCT_OK) s = check_hip(hipMalloc(&p->d_invv, sizeof(double) * geom->nv), "plan table allocation");
+    if (s == KCT_OK) s = check_hip(hipMalloc(&p->d_err, sizeof(int)), "plan flag allocation");
+    if (s == KCT_OK)
+        s = check_hip(hipMemcpy(p->d_tab, p->host_tab.data(), sizeof(AngleGeo) * geom->n_angles,
+                                hipMemcpyHostToDevice), "plan table upload");
+    if (s == KCT_OK)
+        s = check_hip(hipMemcpy(p->d_invv, invv.data(), sizeof(double) * geom->nv, hipMemcpyHostToDevice),
+                      "plan table upload");
+    if (s == KCT_OK) s = check_hip(hipMemset(p->d_err, 0, sizeof(int)), "plan flag reset");
+    if (s != KCT_OK) {
+        kct_plan_destroy(p);
+        return s;
+    }
+    *out = p;
+    return KCT_OK;
+}
+
+kct_status kct_plan_destroy(kct_plan *p)
+{
+    if (!p) return KCT_OK;
+    DeviceGuard dg(p->device);
+    if (p->d_tab) (void)hipFree(p->d_tab);
+    if (p->d_invv) (void)hipFree(p->d_invv);
+    if (p->d_err) (void)hipFree(p->d_err);
+    if (p->d_pad) (void)hipFree(p->d_pad);
+    delete p;
+    return KCT_OK;
+}
+
+kct_status kct_plan_device_bytes(const kct_plan *p, size_t *bytes)
+{
+    if (!p || !bytes) return fail(KCT_E_INVALID_ARG, "NULL argument");
+    *bytes = sizeof(AngleGeo) * p->gp.na + sizeof(double) * p->gp.nv + sizeof(int) + p->pad_bytes;
+    return KCT_OK;
+}
+
+kct_status kct_forward(kct_plan *p, const void *d_vol, int32_t vol_dtype, void *d_proj, int32_t proj_dtype,
+                       void *stream)
+{
+    g_last_error.clear();
+    if (!p || !d_vol || !d_proj) return fail(KCT_E_INVALID_ARG, "NULL argument");
+    if (!dtype_ok(vol_dtype) || !dtype_ok(proj_dtype)) return fail(KCT_E_DTYPE, "unknown storage type");
+    DeviceGuard dg(p->device);
+    const size_t need = size_t(2 * p->pad.vox) * dtype_size(vol_dtype);
+    if (p->pad_bytes < need) {
+        if (p->d_pad) (void)hipFree(p->d_pad);
+        p->d_pad = nullptr;
+        p->pad_bytes = 0;
+        kct_status s = check_hip(hipMalloc(&p->d_pad, need), "padded volume allocation");
+        if (s != KCT_OK) return s;
+        p->pad_bytes = need;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    kct_status s = launch_pad_volume(*p, d_vol, vol_dtype, p->d_pad, st);
+    if (s != KCT_OK) return s;
+    Epilogue ep;
+    return launch_forward(*p, p->d_pad, vol_dtype, d_proj, proj_dtype, ep, st);
+}
+
+kct_status kct_backproject(kct_plan *p, const void *d_proj, int32_t proj_dtype, void *d_vol, int32_t vol_dtype,
+                           void *stream)
+{
+    g_last_error.clear();
+    if (!p || !d_vol || !d_proj) return fail(KCT_E_INVALID_ARG, "NULL argument");
+    if (!dtype_ok(vol_dtype) || !dtype_ok(proj_dtype)) return fail(KCT_E_DTYPE, "unknown storage type");
+    DeviceGuard dg(p->device);
+    Epilogue ep;
+    return launch_backward(*p, d_proj, proj_dtype, d_vol, vol_dtype, ep, static_cast<hipStream_t>(stream));
+}
+
+// Test hook (not in kct.h): read and clear the back projector's footprint
+// overflow flag.  Synchronises the device.
+int kct_debug_take_error_flag(kct_plan *p)
+{
+    if (!p) return -1;
+    DeviceGuard dg(p->device);
+    int v = 0;
+    if (hipDeviceSynchronize() != hipSuccess) return -1;
+    if (hipMemcpy(&v, p->d_err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return -1;
+    (void)hipMemset(p->d_err, 0, sizeof(int));
+    return v;
+}
+
+// Test hook: the back projector launch shape chosen for the plan.
+void kct_debug_bwd_shape(const kct_plan *p, int *kz, int *ncmax, int *pw, int *ph)
+{
+    if (!p) return;
+    if (kz) *kz = p->bwd_kz;
+    if (ncmax) *ncmax = p->bwd_ncmax;
+    if (pw) *pw = p->bwd_pw;
+    if (ph) *ph = p->bwd_ph;
+}
+
+} // extern "C"

@@ -1,0 +1,362 @@
+// Matched back projection x = A^T y, gfx950.
+//
+// Exact transpose of the forward projector: x_j = sum_i a_ij y_i with the
+// same a_ij = length (mm) of ray i inside voxel j.  The forward kernel walks
+// rays; this kernel gathers per voxel, so no atomics and a fixed summation
+// order (bitwise reproducible).  For voxel j and angle t it enumerates the
+// pixels whose centres fall inside the perspective footprint of the voxel (the
+// box spanned by its projected corners, which contains the projection of the
+// whole convex voxel) and intersects each pixel's ray with the voxel's three
+// slabs in FP64:
+//     t in [(x0-sx)/dx, (x1-sx)/dx] n [(y0-sy)/dy, ...] n [z0/v, z1/v],
+// length = (t_hi - t_lo)+ * |d|.  Rays whose centre lies outside the footprint
+// meet the voxel in at most a point, so the sum equals the forward
+// projector's row-wise sum up to rounding.
+//
+// Structure (flat circular detector, e_v = z): the x/y slab interval of a ray
+// depends only on its detector column u, the z interval only on its row v.  A
+// thread owns one (i, j) voxel column and KZ voxels along z, so the per-column
+// x/y intervals are computed once per angle and reused by its KZ voxels; each
+// candidate pixel then costs a max, a min, a subtraction and one FMA with the
+// staged value.  A workgroup is a 16 x 16 x KZ voxel tile; per angle it stages
+// the tile's detector footprint (values pre-multiplied by the ray length |d|)
+// and the per-column 1/dx, 1/dy and per-row 1/v in LDS.
+
+#include "kct_internal.hpp"
+
+#include <algorithm>
+#include <cmath>
+
+namespace kct {
+
+namespace {
+
+constexpr int BWD_TX = 16, BWD_TY = 16;
+
+__device__ inline double block_sum_256b(double v, double *red)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) s = ((red[0] + red[1]) + red[2]) + red[3];
+    return s;
+}
+
+template <typename TP, typename TV, int KZ, int NCM>
+__global__ __launch_bounds__(256) void k_backward(const TP *__restrict__ proj, TV *__restrict__ vol,
+                                                  const AngleGeo *__restrict__ tab,
+                                                  const double *__restrict__ invv, GeoParams g, int tiles_x,
+                                                  int tiles_y, int64_t groups, int pw_max, int ph_max,
+                                                  int *err_flag, Epilogue ep)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    double *cinv = reinterpret_cast<double *>(lds_raw);  // 2 * pw_max
+    double *rinv = cinv + 2 * pw_max;                    // ph_max
+    float *patch = reinterpret_cast<float *>(rinv + ph_max); // pw_max * ph_max + NCM
+    __shared__ double red[4];
+
+    const int64_t g8 = (groups + 7) / 8;
+    const int64_t b = blockIdx.x;
+    const int64_t logical = (b & 7) * g8 + (b >> 3);
+    if (logical >= groups) return;
+    if (ep.scal && ep.scal[S_DONE] != 0.0) return;
+
+    double c0 = ep.c[0], c1 = ep.c[1], c2 = ep.c[2], c3 = ep.c[3];
+    if (ep.coef_idx >= 0) {
+        c0 = ep.scal[ep.coef_idx];
+        c1 = ep.scal[ep.coef_idx + 1];
+        c2 = ep.scal[ep.coef_idx + 2];
+        c3 = ep.scal[ep.coef_idx + 3];
+    }
+
+    const int per_z = tiles_x * tiles_y;
+    const int tz = int(logical / per_z);
+    const int rem = int(logical - int64_t(tz) * per_z);
+    const int tyi = rem / tiles_x, txi = rem - tyi * tiles_x;
+    const int lx = threadIdx.x & 15, ly = threadIdx.x >> 4;
+    const int i = txi * BWD_TX + lx, j = tyi * BWD_TY + ly, k0 = tz * KZ;
+    const bool valid = i < g.nx && j < g.ny;
+
+    const double x0 = g.X0 + i * g.vx, x1 = x0 + g.vx;
+    const double y0 = g.Y0 + j * g.vy, y1 = y0 + g.vy;
+    const int ie = min(txi * BWD_TX + BWD_TX, g.nx), je = min(tyi * BWD_TY + BWD_TY, g.ny);
+    const int ke = min(k0 + KZ, g.nz);
+    const float tx0 = float(g.X0 + txi * BWD_TX * g.vx), tx1 = float(g.X0 + ie * g.vx);
+    const float ty0 = float(g.Y0 + tyi * BWD_TY * g.vy), ty1 = float(g.Y0 + je * g.vy);
+    const float tz0 = float(g.Z0 + k0 * g.vz), tz1 = float(g.Z0 + ke * g.vz);
+    const float dsd = float(g.dsd), dso = float(g.dso);
+    const float idu = float(1.0 / g.du), idv = float(1.0 / g.dv), cu = float(g.cu), cv = float(g.cv);
+    const float margin = 0.01f; // pixels; the exact FP64 intervals reject extra candidates
+    constexpr double FAR = 1.0e300;
+
+    float acc[KZ];
+#pragma unroll
+    for (int kk = 0; kk < KZ; ++kk) acc[kk] = 0.f;
+
+    for (int a = 0; a < g.na; ++a) {
+        const AngleGeo A = tab[a];
+        const float cs = float(A.cs), sn = float(A.sn);
+        // Footprint of the whole tile (identical on every thread).
+        float umin = 3.0e38f, umax = -3.0e38f, wmin = 3.0e38f, wmax = -3.0e38f;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float x = (q & 1) ? tx1 : tx0, y = (q & 2) ? ty1 : ty0;
+            const float w = dso - (x * cs + y * sn);
+            const float l = -x * sn + y * cs;
+            const float u = dsd * l / w;
+            umin = fminf(umin, u); umax = fmaxf(umax, u);
+            wmin = fminf(wmin, w); wmax = fmaxf(wmax, w);
+        }
+        const float va = dsd * tz0 / wmin, vb = dsd * tz0 / wmax, vc = dsd * tz1 / wmin, vd = dsd * tz1 / wmax;
+        const float vmin = fminf(fminf(va, vb), fminf(vc, vd)), vmax = fmaxf(fmaxf(va, vb), fmaxf(vc, vd));
+        const int iu_lo = max(0, int(ceilf(umin * idu + cu - margin)));
+        const int iu_hi = min(g.nu - 1, int(floorf(umax * idu + cu + margin)));
+        const int iv_lo = max(0, int(ceilf(vmin * idv + cv - margin)));
+        const int iv_hi = min(g.nv - 1, int(floorf(vmax * idv + cv + margin)));
+        int pw = iu_hi - iu_lo + 1, ph = iv_hi - iv_lo + 1;
+        if (pw <= 0 || ph <= 0) continue;
+        if (pw > pw_max || ph > ph_max) {
+            if (threadIdx.x == 0 && err_flag) atomicOr(err_flag, 1);
+            pw = min(pw, pw_max);
+            ph = min(ph, ph_max);
+        }
+
+        __syncthreads(); // the previous angle's reads of LDS are done
+        const TP *ya = proj + int64_t(a) * g.nv * g.nu;
+        for (int e = threadIdx.x; e < pw * ph; e += 256) {
+            const int r = e / pw, c = e - r * pw;
+            const int iu = iu_lo + c, iv = iv_lo + r;
+            const float uu = float((iu - g.cu) * g.du), vv = float((iv - g.cv) * g.dv);
+            const float yv = to_f32(ya[int64_t(iv) * g.nu + iu]);
+            patch[e] = yv * sqrtf(dsd * dsd + uu * uu + vv * vv);
+        }
+        for (int c = threadIdx.x; c < pw; c += 256) {
+            // 1/d per axis; 0 marks a ray parallel to that axis's planes.
+            const double u = (iu_lo + c - g.cu) * g.du;
+            const double dxm = -g.dsd * A.cs - u * A.sn, dym = -g.dsd * A.sn + u * A.cs;
+            cinv[2 * c] = dxm != 0.0 ? 1.0 / dxm : 0.0;
+            cinv[2 * c + 1] = dym != 0.0 ? 1.0 / dym : 0.0;
+        }
+        for (int r = threadIdx.x; r < ph; r += 256) rinv[r] = invv[iv_lo + r];
+        __syncthreads();
+
+        if (valid) {
+            // Own column footprint.
+            float cumin = 3.0e38f, cumax = -3.0e38f, cwmin = 3.0e38f, cwmax = -3.0e38f;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float x = float((q & 1) ? x1 : x0), y = float((q & 2) ? y1 : y0);
+                const float w = dso - (x * cs + y * sn);
+                const float l = -x * sn + y * cs;
+                const float u = dsd * l / w;
+                cumin = fminf(cumin, u); cumax = fmaxf(cumax, u);
+                cwmin = fminf(cwmin, w); cwmax = fmaxf(cwmax, w);
+            }
+            const int c_lo = max(iu_lo, int(ceilf(cumin * idu + cu - margin)));
+            int nc = min(iu_hi, int(floorf(cumax * idu + cu + margin))) - c_lo + 1;
+            if (nc > NCM) {
+                if (err_flag) atomicOr(err_flag, 2);
+                nc = NCM;
+            }
+            nc = min(nc, pw - (c_lo - iu_lo)); // stay inside the staged patch
+            const double ax0 = x0 - A.sx, ax1 = x1 - A.sx, ay0 = y0 - A.sy, ay1 = y1 - A.sy;
+            double lo[NCM], hi[NCM];
+#pragma unroll
+            for (int c = 0; c < NCM; ++c) {
+                lo[c] = 1.0;
+                hi[c] = 0.0;
+                if (c < nc) {
+                    const int ci = c_lo - iu_lo + c;
+                    const double ix = cinv[2 * ci], iy = cinv[2 * ci + 1];
+                    double xl, xh, yl, yh;
+                    if (ix != 0.0) {
+                        const double ta = ax0 * ix, tb = ax1 * ix;
+                        xl = fmin(ta, tb);
+                        xh = fmax(ta, tb);
+                    } else { // parallel to x-planes: inside iff x0 <= sx < x1
+                        const bool in = ax0 <= 0.0 && 0.0 < ax1;
+                        xl = in ? -FAR : FAR;
+                        xh = in ? FAR : -FAR;
+                    }
+                    if (iy != 0.0) {
+                        const double tc = ay0 * iy, td = ay1 * iy;
+                        yl = fmin(tc, td);
+                        yh = fmax(tc, td);
+                    } else {
+                        const bool in = ay0 <= 0.0 && 0.0 < ay1;
+                        yl = in ? -FAR : FAR;
+                        yh = in ? FAR : -FAR;
+                    }
+                    lo[c] = fmax(xl, yl);
+                    hi[c] = fmin(xh, yh);
+                }
+            }
+            const float *pcol = patch + (c_lo - iu_lo);
+            const float rwmin = 1.0f / cwmin, rwmax = 1.0f / cwmax;
+#pragma unroll
+            for (int kk = 0; kk < KZ; ++kk) {
+                const int k = k0 + kk;
+                if (k < g.nz && nc > 0) {
+                    const double z0 = g.Z0 + k * g.vz, z1 = z0 + g.vz;
+                    const float fz0 = float(z0), fz1 = float(z1);
+                    const float pa = dsd * fz0 * rwmin, pb = dsd * fz0 * rwmax, pc = dsd * fz1 * rwmin,
+                                pd = dsd * fz1 * rwmax;
+                    const float pmin = fminf(fminf(pa, pb), fminf(pc, pd));
+                    const float pmax = fmaxf(fmaxf(pa, pb), fmaxf(pc, pd));
+                    const int r_lo = max(iv_lo, int(ceilf(pmin * idv + cv - margin)));
+                    const int r_hi = min(iv_lo + ph - 1, int(floorf(pmax * idv + cv + margin)));
+                    float s = acc[kk];
+                    for (int r = r_lo; r <= r_hi; ++r) {
+                        const double iv = rinv[r - iv_lo];
+                        double zl, zh;
+                        if (iv != 0.0) {
+                            const double ta = z0 * iv, tb = z1 * iv;
+                            zl = fmin(ta, tb);
+                            zh = fmax(ta, tb);
+                        } else {
+                            const bool in = z0 <= 0.0 && 0.0 < z1;
+                            zl = in ? -FAR : FAR;
+                            zh = in ? FAR : -FAR;
+                        }
+                        const float *prow = pcol + (r - iv_lo) * pw;
+#pragma unroll
+                        for (int c = 0; c < NCM; ++c) {
+                            const double len = fmin(hi[c], zh) - fmax(lo[c], zl);
+                            s = fmaf(float(fmax(len, 0.0)), prow[c], s);
+                        }
+                    }
+                    acc[kk] = s;
+                }
+            }
+        }
+    }
+
+    double part = 0.0;
+    if (valid) {
+#pragma unroll
+        for (int kk = 0; kk < KZ; ++kk) {
+            const int k = k0 + kk;
+            if (k < g.nz) {
+                const int64_t idx = (int64_t(k) * g.ny + j) * g.nx + i;
+                double o = c0 * double(acc[kk]);
+                if (ep.in1) o += c1 * double(to_f32(static_cast<const TV *>(ep.in1)[idx]));
+                if (ep.in2) o += c2 * double(ep.in2[idx]);
+                if (ep.in3) o += c3 * double(to_f32(static_cast<const TV *>(ep.in3)[idx]));
+                const TV st = from_f32<TV>(float(o));
+                vol[idx] = st;
+                const double sv = double(to_f32(st));
+                part += sv * sv;
+            }
+        }
+    }
+    if (ep.partials) {
+        const double s = block_sum_256b(part, red);
+        if (threadIdx.x == 0) ep.partials[logical] = s;
+    }
+}
+
+struct BwdShape {
+    int64_t tiles_x, tiles_y, tiles_z, groups;
+};
+
+BwdShape bwd_shape(const Plan &p)
+{
+    BwdShape s;
+    s.tiles_x = (p.gp.nx + BWD_TX - 1) / BWD_TX;
+    s.tiles_y = (p.gp.ny + BWD_TY - 1) / BWD_TY;
+    s.tiles_z = (p.gp.nz + p.bwd_kz - 1) / p.bwd_kz;
+    s.groups = s.tiles_x * s.tiles_y * s.tiles_z;
+    return s;
+}
+
+template <typename TP, typename TV, int KZ, int NCM>
+kct_status bwd_launch3(Plan &p, const void *proj, void *vol, const Epilogue &ep, hipStream_t st)
+{
+    const BwdShape s = bwd_shape(p);
+    const int64_t launch = ((s.groups + 7) / 8) * 8;
+    hipLaunchKernelGGL((k_backward<TP, TV, KZ, NCM>), dim3(unsigned(launch)), dim3(256), p.bwd_lds, st,
+                       static_cast<const TP *>(proj), static_cast<TV *>(vol), p.d_tab, p.d_invv, p.gp,
+                       int(s.tiles_x), int(s.tiles_y), s.groups, p.bwd_pw, p.bwd_ph, p.d_err, ep);
+    return check_hip(hipGetLastError(), "back projection launch");
+}
+
+template <typename TP, typename TV, int KZ>
+kct_status bwd_launch2(Plan &p, const void *proj, void *vol, const Epilogue &ep, hipStream_t st)
+{
+    switch (p.bwd_ncmax) {
+    case 2: return bwd_launch3<TP, TV, KZ, 2>(p, proj, vol, ep, st);
+    case 3: return bwd_launch3<TP, TV, KZ, 3>(p, proj, vol, ep, st);
+    case 4: return bwd_launch3<TP, TV, KZ, 4>(p, proj, vol, ep, st);
+    case 8: return bwd_launch3<TP, TV, KZ, 8>(p, proj, vol, ep, st);
+    }
+    return fail(KCT_E_GEOMETRY, "unsupported back projector footprint width");
+}
+
+template <typename TP, typename TV>
+kct_status bwd_launch1(Plan &p, const void *proj, void *vol, const Epilogue &ep, hipStream_t st)
+{
+    if (p.bwd_kz == 8) return bwd_launch2<TP, TV, 8>(p, proj, vol, ep, st);
+    return bwd_launch2<TP, TV, 1>(p, proj, vol, ep, st);
+}
+
+} // namespace
+
+int64_t bwd_num_groups(const Plan &p) { return bwd_shape(p).groups; }
+
+// Bounds that size the launch: the widest per-voxel footprint (columns) and
+// the largest per-tile detector patch, from the extreme magnification of the
+// volume's bounding cylinder.  The kernel clamps to these sizes (and raises a
+// flag) if they were ever exceeded, so LDS is never overrun.
+kct_status choose_bwd_shape(Plan &p)
+{
+    const GeoParams &g = p.gp;
+    const double xs[2] = {g.X0, g.X0 + g.nx * g.vx}, ys[2] = {g.Y0, g.Y0 + g.ny * g.vy};
+    double R = 0.0;
+    for (double x : xs)
+        for (double y : ys) R = std::max(R, std::sqrt(x * x + y * y));
+    const double zmax = std::max(std::fabs(g.Z0), std::fabs(g.Z0 + g.nz * g.vz));
+    const double wmin = g.dso - R;
+    if (wmin <= 0.0) return fail(KCT_E_GEOMETRY, "volume reaches the source orbit");
+    const double mag = g.dsd / wmin * (1.0 + R / wmin);
+    const double vox_diag = std::sqrt(g.vx * g.vx + g.vy * g.vy);
+    const double ncols = std::floor(vox_diag * mag / g.du + 0.02) + 1.0;
+    int ncm = 0;
+    for (int c : {2, 3, 4, 8})
+        if (ncols <= c) { ncm = c; break; }
+    if (!ncm) return fail(KCT_E_GEOMETRY, "voxels project onto more than 8 detector columns");
+    p.bwd_ncmax = ncm;
+
+    // Enough workgroups to fill 256 CUs several times over, else one voxel per thread.
+    const int64_t txy = int64_t((g.nx + BWD_TX - 1) / BWD_TX) * ((g.ny + BWD_TY - 1) / BWD_TY);
+    p.bwd_kz = (txy * ((g.nz + 7) / 8) >= 2048) ? 8 : 1;
+    for (;;) {
+        const double tdiag = std::sqrt(std::pow(BWD_TX * g.vx, 2) + std::pow(BWD_TY * g.vy, 2));
+        const double pw = std::floor(tdiag * mag / g.du + 0.02) + 2.0;
+        const double ph = std::floor(g.dsd * (p.bwd_kz * g.vz / wmin + zmax * tdiag / (wmin * wmin)) / g.dv +
+                                     0.02) + 2.0;
+        p.bwd_pw = int(std::min<double>(pw, g.nu));
+        p.bwd_ph = int(std::min<double>(ph, g.nv));
+        p.bwd_lds = size_t(p.bwd_pw) * 16 + size_t(p.bwd_ph) * 8 +
+                    (size_t(p.bwd_pw) * p.bwd_ph + 8) * sizeof(float);
+        if (p.bwd_lds <= 64 * 1024) return KCT_OK;
+        if (p.bwd_kz == 1) return fail(KCT_E_GEOMETRY, "detector footprint of a voxel tile exceeds LDS");
+        p.bwd_kz = 1;
+    }
+}
+
+kct_status launch_backward(Plan &p, const void *proj, int proj_dtype, void *vol, int vol_dtype,
+                           const Epilogue &ep, hipStream_t st)
+{
+    if (proj_dtype == KCT_F32 && vol_dtype == KCT_F32) return bwd_launch1<float, float>(p, proj, vol, ep, st);
+    if (proj_dtype == KCT_BF16 && vol_dtype == KCT_BF16) return bwd_launch1<bf16, bf16>(p, proj, vol, ep, st);
+    if (proj_dtype == KCT_F16 && vol_dtype == KCT_F16) return bwd_launch1<_Float16, _Float16>(p, proj, vol, ep, st);
+    if (proj_dtype == KCT_BF16 && vol_dtype == KCT_F32) return bwd_launch1<bf16, float>(p, proj, vol, ep, st);
+    if (proj_dtype == KCT_F16 && vol_dtype == KCT_F32) return bwd_launch1<_Float16, float>(p, proj, vol, ep, st);
+    if (proj_dtype == KCT_F32 && vol_dtype == KCT_BF16) return bwd_launch1<float, bf16>(p, proj, vol, ep, st);
+    if (proj_dtype == KCT_F32 && vol_dtype == KCT_F16) return bwd_launch1<float, _Float16>(p, proj, vol, ep, st);
+    return fail(KCT_E_DTYPE, "unsupported (projection, volume) storage pair for back projection");
+}
+
+} // namespace kct

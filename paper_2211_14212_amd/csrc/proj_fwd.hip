@@ -1,0 +1,285 @@
+// Forward cone-beam projection y = A x (Siddon path lengths), gfx950.
+//
+// One thread traces one ray (source -> pixel centre) through the voxel grid
+// and accumulates length * value in FP32.  The ray geometry (entry point,
+// plane crossings) is evaluated in FP64, which runs at the non-packed FP32
+// rate on CDNA4, so the per-coefficient length carries ~1e-16 relative error
+// instead of the ~1e-5 an FP32 parametrisation of a 256-voxel ray would.
+//
+// Launch shape: a workgroup is 64 adjacent pixels of 4 adjacent detector rows
+// of one angle (one wave per row), so the lanes of a wave trace neighbouring
+// rays that cross the same voxel columns.  Lanes map to u, and neighbouring u
+// are displaced along e_u, which is close to y for angles with |cos| >= |sin|:
+// for those angles the kernel reads a y-fastest copy of the volume so that a
+// wave's gather touches a few contiguous runs instead of 64 scattered lines.
+// Both copies carry a one-voxel zero border, which makes a one-step overshoot
+// at the exit face (possible when a crossing rounds to just before the exit
+// parameter) read zero instead of leaving the buffer.
+//
+// Workgroups are renumbered so that the 8 XCDs (round-robin dispatch) each
+// take a contiguous block of angles: rays of one angle share the voxels they
+// cross, so each XCD's L2 holds one angle's working set.
+
+#include "kct_internal.hpp"
+
+namespace kct {
+
+namespace {
+
+constexpr int FWD_TU = 64; // pixels along u per workgroup (one wave)
+constexpr int FWD_TV = 4;  // detector rows per workgroup (one wave each)
+
+// --------------------------------------------------------------------------
+// Padded volume copies: out[0:vox] x-fastest, out[vox:2vox] y-fastest, both
+// (nz+2) x (ny+2) x (nx+2) with a zero border.  32x32 xy tiles through LDS
+// so that both writes are coalesced.
+// --------------------------------------------------------------------------
+template <typename TIN, typename TOUT>
+__global__ __launch_bounds__(256) void k_pad_volume(const TIN *__restrict__ in, TOUT *__restrict__ out,
+                                                    int nx, int ny, int nz, PadLayout pl)
+{
+    __shared__ float tile[32][33];
+    const int tiles_x = int((pl.px + 31) / 32);
+    const int bx = blockIdx.x % tiles_x, by = blockIdx.x / tiles_x;
+    const int64_t pk = blockIdx.y; // padded z index
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5; // 32 x 8
+    const int64_t k = pk - 1;
+    // Load: padded (pi, pj) = (bx*32 + tx, by*32 + ty + 8r).
+    for (int r = 0; r < 4; ++r) {
+        const int64_t pi = int64_t(bx) * 32 + tx, pj = int64_t(by) * 32 + ty + 8 * r;
+        float v = 0.f;
+        const int64_t i = pi - 1, j = pj - 1;
+        if (i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz)
+            v = to_f32(in[(k * ny + j) * nx + i]);
+        tile[ty + 8 * r][tx] = v;
+        if (pi < pl.px && pj < pl.py) out[(pk * pl.py + pj) * pl.px + pi] = from_f32<TOUT>(v);
+    }
+    __syncthreads();
+    // Transposed write: element (pk, pi, pj) at (pk*px + pi)*py + pj, pj fastest.
+    for (int r = 0; r < 4; ++r) {
+        const int64_t pj = int64_t(by) * 32 + tx, pi = int64_t(bx) * 32 + ty + 8 * r;
+        if (pi < pl.px && pj < pl.py)
+            out[pl.vox + (pk * pl.px + pi) * pl.py + pj] = from_f32<TOUT>(tile[tx][ty + 8 * r]);
+    }
+}
+
+// Deterministic workgroup sum of one double per thread (256 threads).
+__device__ inline double block_sum_256(double v, double *red)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) s = ((red[0] + red[1]) + red[2]) + red[3];
+    return s;
+}
+
+template <typename TV, typename TP, typename IDX>
+__global__ __launch_bounds__(256) void k_forward(const TV *__restrict__ vpad, TP *__restrict__ proj,
+                                                 const AngleGeo *__restrict__ tab, GeoParams g, PadLayout pl,
+                                                 int tiles_u, int tiles_v, int64_t groups, Epilogue ep)
+{
+    __shared__ double red[4];
+    const int64_t g8 = (groups + 7) / 8;
+    const int64_t b = blockIdx.x;
+    const int64_t logical = (b & 7) * g8 + (b >> 3);
+    if (logical >= groups) return;
+    if (ep.scal && ep.scal[S_DONE] != 0.0) return;
+
+    double c0 = ep.c[0], c1 = ep.c[1];
+    if (ep.coef_idx >= 0) {
+        c0 = ep.scal[ep.coef_idx];
+        c1 = ep.scal[ep.coef_idx + 1];
+    }
+
+    const int per_angle = tiles_u * tiles_v;
+    const int a = int(logical / per_angle);
+    const int rem = int(logical - int64_t(a) * per_angle);
+    const int tvi = rem / tiles_u, tui = rem - tvi * tiles_u;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int iu = tui * FWD_TU + lane, iv = tvi * FWD_TV + wv;
+    const bool valid = iu < g.nu && iv < g.nv;
+
+    const AngleGeo A = tab[a];
+    float acc = 0.f;
+    double dn = 0.0;
+    if (valid) {
+        const double u = (iu - g.cu) * g.du, v = (iv - g.cv) * g.dv;
+        const double dx = A.d0x + u * A.eux, dy = A.d0y + u * A.euy, dz = v * g.ivz;
+        dn = sqrt(g.dsd * g.dsd + u * u + v * v);
+        double tmin = 0.0, tmax = 1.0;
+        double inx = 0.0, iny = 0.0, inz = 0.0;
+        if (dx != 0.0) {
+            inx = 1.0 / dx;
+            const double t0 = (0.0 - A.svx) * inx, t1 = (double(g.nx) - A.svx) * inx;
+            tmin = fmax(tmin, fmin(t0, t1));
+            tmax = fmin(tmax, fmax(t0, t1));
+        } else if (!(A.svx >= 0.0 && A.svx < g.nx)) {
+            tmax = -1.0;
+        }
+        if (dy != 0.0) {
+            iny = 1.0 / dy;
+            const double t0 = (0.0 - A.svy) * iny, t1 = (double(g.ny) - A.svy) * iny;
+            tmin = fmax(tmin, fmin(t0, t1));
+            tmax = fmin(tmax, fmax(t0, t1));
+        } else if (!(A.svy >= 0.0 && A.svy < g.ny)) {
+            tmax = -1.0;
+        }
+        if (dz != 0.0) {
+            inz = 1.0 / dz;
+            const double t0 = (0.0 - A.svz) * inz, t1 = (double(g.nz) - A.svz) * inz;
+            tmin = fmax(tmin, fmin(t0, t1));
+            tmax = fmin(tmax, fmax(t0, t1));
+        } else if (!(A.svz >= 0.0 && A.svz < g.nz)) {
+            tmax = -1.0;
+        }
+        if (tmin < tmax) {
+            const int i = min(max(int(floor(A.svx + tmin * dx)), 0), g.nx - 1);
+            const int j = min(max(int(floor(A.svy + tmin * dy)), 0), g.ny - 1);
+            const int k = min(max(int(floor(A.svz + tmin * dz)), 0), g.nz - 1);
+            // Element strides of the chosen padded copy.
+            const int64_t sx = A.transposed ? pl.py : 1;
+            const int64_t sy = A.transposed ? 1 : pl.px;
+            const int64_t sz = pl.px * pl.py;
+            const int64_t base = A.transposed ? pl.vox : 0;
+            constexpr double FAR = 1.0e300;
+            double tx = FAR, ty = FAR, tz = FAR, dtx = 0.0, dty = 0.0, dtz = 0.0;
+            IDX stx = 0, sty = 0, stz = 0;
+            if (dx > 0.0) { tx = (i + 1 - A.svx) * inx; dtx = inx; stx = IDX(sx); }
+            else if (dx < 0.0) { tx = (i - A.svx) * inx; dtx = -inx; stx = IDX(-sx); }
+            if (dy > 0.0) { ty = (j + 1 - A.svy) * iny; dty = iny; sty = IDX(sy); }
+            else if (dy < 0.0) { ty = (j - A.svy) * iny; dty = -iny; sty = IDX(-sy); }
+            if (dz > 0.0) { tz = (k + 1 - A.svz) * inz; dtz = inz; stz = IDX(sz); }
+            else if (dz < 0.0) { tz = (k - A.svz) * inz; dtz = -inz; stz = IDX(-sz); }
+            IDX idx = IDX(base + (i + 1) * sx + (j + 1) * sy + (k + 1) * sz);
+            double tc = tmin;
+            // A ray crosses at most nx+ny+nz+3 planes; the cap only guarantees
+            // termination if rounding ever produced a non-advancing step.
+            int guard = g.nx + g.ny + g.nz + 8;
+            do {
+                const double tn = fmin(fmin(tx, ty), fmin(tz, tmax));
+                const float val = to_f32(vpad[idx]);
+                acc = fmaf(float(tn - tc), val, acc);
+                tc = tn;
+                const bool cx = tx <= tn, cy = ty <= tn, cz = tz <= tn;
+                tx = cx ? tx + dtx : tx;
+                ty = cy ? ty + dty : ty;
+                tz = cz ? tz + dtz : tz;
+                idx += (cx ? stx : IDX(0)) + (cy ? sty : IDX(0)) + (cz ? stz : IDX(0));
+            } while (tc < tmax && --guard > 0);
+        }
+    }
+
+    float outv = 0.f;
+    if (valid) {
+        const int64_t ray = (int64_t(a) * g.nv + iv) * g.nu + iu;
+        double o = c0 * (double(acc) * dn);
+        if (ep.in1) o += c1 * double(to_f32(static_cast<const TP *>(ep.in1)[ray]));
+        const TP st = from_f32<TP>(float(o));
+        proj[ray] = st;
+        outv = to_f32(st);
+    }
+    if (ep.partials) {
+        const double s = block_sum_256(double(outv) * double(outv), red);
+        if (threadIdx.x == 0) ep.partials[logical] = s;
+    }
+}
+
+template <typename TIN, typename TOUT>
+kct_status pad_typed(Plan &p, const void *vol, void *pad, hipStream_t st)
+{
+    const int tiles_x = int((p.pad.px + 31) / 32), tiles_y = int((p.pad.py + 31) / 32);
+    dim3 grid(unsigned(tiles_x * tiles_y), unsigned(p.pad.pz));
+    hipLaunchKernelGGL((k_pad_volume<TIN, TOUT>), grid, dim3(256), 0, st, static_cast<const TIN *>(vol),
+                       static_cast<TOUT *>(pad), p.gp.nx, p.gp.ny, p.gp.nz, p.pad);
+    return check_hip(hipGetLastError(), "pad volume launch");
+}
+
+template <typename TV, typename TP>
+kct_status fwd_typed(Plan &p, const void *pad, void *proj, const Epilogue &ep, hipStream_t st)
+{
+    const int tiles_u = (p.gp.nu + FWD_TU - 1) / FWD_TU, tiles_v = (p.gp.nv + FWD_TV - 1) / FWD_TV;
+    const int64_t groups = int64_t(p.gp.na) * tiles_u * tiles_v;
+    const int64_t launch = ((groups + 7) / 8) * 8;
+    if (launch > int64_t(0x7fffffff)) return fail(KCT_E_GEOMETRY, "forward projection grid too large");
+    const bool small = 2 * p.pad.vox < int64_t(0xffffffffLL);
+    if (small)
+        hipLaunchKernelGGL((k_forward<TV, TP, uint32_t>), dim3(unsigned(launch)), dim3(256), 0, st,
+                           static_cast<const TV *>(pad), static_cast<TP *>(proj), p.d_tab, p.gp, p.pad,
+                           tiles_u, tiles_v, groups, ep);
+    else
+        hipLaunchKernelGGL((k_forward<TV, TP, uint64_t>), dim3(unsigned(launch)), dim3(256), 0, st,
+                           static_cast<const TV *>(pad), static_cast<TP *>(proj), p.d_tab, p.gp, p.pad,
+                           tiles_u, tiles_v, groups, ep);
+    return check_hip(hipGetLastError(), "forward projection launch");
+}
+
+template <typename TIN>
+kct_status pad_dispatch_out(Plan &p, const void *vol, int out_dt, void *pad, hipStream_t st)
+{
+    switch (out_dt) {
+    case KCT_F32: return pad_typed<TIN, float>(p, vol, pad, st);
+    case KCT_BF16: return pad_typed<TIN, bf16>(p, vol, pad, st);
+    case KCT_F16: return pad_typed<TIN, _Float16>(p, vol, pad, st);
+    }
+    return fail(KCT_E_DTYPE, "unsupported volume storage type");
+}
+
+template <typename TV>
+kct_status fwd_dispatch_proj(Plan &p, const void *pad, void *proj, int proj_dt, const Epilogue &ep,
+                             hipStream_t st)
+{
+    switch (proj_dt) {
+    case KCT_F32: return fwd_typed<TV, float>(p, pad, proj, ep, st);
+    case KCT_BF16: return fwd_typed<TV, bf16>(p, pad, proj, ep, st);
+    case KCT_F16: return fwd_typed<TV, _Float16>(p, pad, proj, ep, st);
+    }
+    return fail(KCT_E_DTYPE, "unsupported projection storage type");
+}
+
+} // namespace
+
+// Build both padded copies of `vol` (storage `dtype`) in `pad`, stored in
+// the same type.  `pad` must hold 2 * pad.vox elements of that type.
+kct_status launch_pad_volume(Plan &p, const void *vol, int dtype, void *pad, hipStream_t st)
+{
+    switch (dtype) {
+    case KCT_F32: return pad_dispatch_out<float>(p, vol, dtype, pad, st);
+    case KCT_BF16: return pad_dispatch_out<bf16>(p, vol, dtype, pad, st);
+    case KCT_F16: return pad_dispatch_out<_Float16>(p, vol, dtype, pad, st);
+    }
+    return fail(KCT_E_DTYPE, "unsupported volume storage type");
+}
+
+// As launch_pad_volume, converting from `in_dtype` to `out_dtype` storage.
+kct_status launch_pad_volume_as(Plan &p, const void *vol, int in_dtype, int out_dtype, void *pad, hipStream_t st)
+{
+    switch (in_dtype) {
+    case KCT_F32: return pad_dispatch_out<float>(p, vol, out_dtype, pad, st);
+    case KCT_BF16: return pad_dispatch_out<bf16>(p, vol, out_dtype, pad, st);
+    case KCT_F16: return pad_dispatch_out<_Float16>(p, vol, out_dtype, pad, st);
+    }
+    return fail(KCT_E_DTYPE, "unsupported volume storage type");
+}
+
+int64_t fwd_num_groups(const Plan &p)
+{
+    const int tiles_u = (p.gp.nu + FWD_TU - 1) / FWD_TU, tiles_v = (p.gp.nv + FWD_TV - 1) / FWD_TV;
+    return int64_t(p.gp.na) * tiles_u * tiles_v;
+}
+
+// Project the padded copies in `pad` (built by launch_pad_volume with
+// `vol_dtype`) into `proj`, applying the epilogue.
+kct_status launch_forward(Plan &p, const void *pad, int vol_dtype, void *proj, int proj_dtype,
+                          const Epilogue &ep, hipStream_t st)
+{
+    switch (vol_dtype) {
+    case KCT_F32: return fwd_dispatch_proj<float>(p, pad, proj, proj_dtype, ep, st);
+    case KCT_BF16: return fwd_dispatch_proj<bf16>(p, pad, proj, proj_dtype, ep, st);
+    case KCT_F16: return fwd_dispatch_proj<_Float16>(p, pad, proj, proj_dtype, ep, st);
+    }
+    return fail(KCT_E_DTYPE, "unsupported volume storage type");
+}
+
+} // namespace kct

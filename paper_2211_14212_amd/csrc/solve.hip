@@ -1,0 +1,470 @@
+// Solver drivers: workspace layout and the per-iteration kernel sequences of
+// CGLS, LSQR, LSMR and hybrid LSQR (paper Sec. 2.1 and Sec. 2.2).  Every
+// step is enqueued on the caller's stream; the Krylov scalars live in device
+// FP64 memory, so the host never waits inside the loop.
+//
+// Per iteration (-> marks a fused epilogue):
+//   CGLS    pad(p); q = A p -> ||q||^2; alpha; r += -alpha q -> ||r||^2;
+//           s = A^T r - lam^2 (x + alpha p) -> ||s||^2; beta;
+//           x += alpha p, p = s + beta p -> ||p||^2
+//   LSQR    pad(V); U = A V / alpha - (alpha/beta) U -> ||U||^2; beta;
+//           V = A^T U / beta - (beta/alpha) V -> ||V||^2; alpha, rotations;
+//           x += (phi/rho) w, w = V/alpha - (theta/rho) w
+//   LSMR    as LSQR, then hbar, x, h updates in one pass
+//   hybrid  as LSQR's bidiagonalisation with V_k kept; at the end the small
+//           projected Tikhonov problem is solved on the device and x = V_k y
+//   IRN-TV  (Sec. 2.3.1) outer k: weights L from x (L = I at k = 0), restart
+//           r1 = b - A x, r2 = -lam L D x, s = A^T r1 + lam D^T L r2, p = s;
+//           inner CGLS on [A; lam L D]: q1 = A p -> ||q1||^2 and
+//           ||lam L D p||^2; alpha; r1 -= alpha q1; r2 -= alpha lam L D p;
+//           s = A^T r1 + lam D^T L r2 -> ||s||^2; beta; x, p updates
+
+#include "krylov.hpp"
+
+#include <cmath>
+#include <new>
+
+namespace kct {
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+
+size_t up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct Layout {
+    size_t scal = 0, pa = 0, pb = 0, pc = 0, stage = 0, gk = 0, work = 0, coef = 0, pad = 0;
+    size_t v[6] = {0, 0, 0, 0, 0, 0};
+    size_t total = 0;
+    int64_t nparts = 0;
+};
+
+bool solver_ok(int s) { return s >= KCT_CGLS && s <= KCT_IRN_TV_CGLS; }
+
+kct_status check_params(const kct_solve_params *prm)
+{
+    if (!prm) return fail(KCT_E_INVALID_ARG, "params is NULL");
+    if (!solver_ok(prm->solver)) return fail(KCT_E_INVALID_ARG, "unknown solver");
+    if (prm->solver == KCT_IRN_TV_CGLS) {
+        if (prm->tv_outer < 1 || prm->tv_inner < 1 || int64_t(prm->tv_outer) * prm->tv_inner > 100000)
+            return fail(KCT_E_INVALID_ARG, "IRN-TV needs tv_outer >= 1 and tv_inner >= 1");
+        if (!(prm->tv_eps > 0.0) || !std::isfinite(prm->tv_eps)) return fail(KCT_E_INVALID_ARG, "tv_eps must be > 0");
+    }
+    if (prm->n_iter < 0 || prm->n_iter > 100000) return fail(KCT_E_INVALID_ARG, "n_iter out of range");
+    if (!(prm->lambda >= 0.0) || !std::isfinite(prm->lambda)) return fail(KCT_E_INVALID_ARG, "lambda must be >= 0");
+    if (!dtype_ok(prm->vec_dtype)) return fail(KCT_E_DTYPE, "unknown vector storage type");
+    return KCT_OK;
+}
+
+Layout layout(const Plan &p, const kct_solve_params &prm)
+{
+    Layout L;
+    const int64_t N = p.n_ray(), M = p.n_vox();
+    const size_t vt = dtype_size(prm.vec_dtype);
+    L.nparts = std::max<int64_t>({fwd_num_groups(p), bwd_num_groups(p), int64_t(VEC_GROUPS)});
+    size_t o = 0;
+    L.scal = o; o += up(sizeof(double) * S_COUNT);
+    L.pa = o; o += up(sizeof(double) * L.nparts);
+    L.pb = o; o += up(sizeof(double) * L.nparts);
+    L.pc = o; o += up(sizeof(double) * L.nparts);
+    L.stage = o; o += up(sizeof(double) * 3 * 256);
+    L.pad = o; o += up(size_t(2 * p.pad.vox) * vt);
+    const int k = prm.n_iter;
+    switch (prm.solver) {
+    case KCT_CGLS:
+        L.v[0] = o; o += up(size_t(N) * vt); // r
+        L.v[1] = o; o += up(size_t(N) * vt); // q
+        L.v[2] = o; o += up(size_t(M) * vt); // p
+        L.v[3] = o; o += up(size_t(M) * vt); // s
+        break;
+    case KCT_LSQR:
+        L.v[0] = o; o += up(size_t(N) * vt); // U
+        L.v[1] = o; o += up(size_t(M) * vt); // V
+        L.v[2] = o; o += up(size_t(M) * 4);  // w
+        break;
+    case KCT_LSMR:
+        L.v[0] = o; o += up(size_t(N) * vt); // U
+        L.v[1] = o; o += up(size_t(M) * vt); // V
+        L.v[2] = o; o += up(size_t(M) * 4);  // h
+        L.v[3] = o; o += up(size_t(M) * 4);  // hbar
+        break;
+    case KCT_HYBRID_LSQR:
+        L.v[0] = o; o += up(size_t(N) * vt);                 // U
+        L.v[1] = o; o += up(size_t(M) * vt * size_t(k + 1)); // basis V_1..V_{k+1}
+        L.gk = o; o += up(sizeof(double) * (2 * size_t(k) + 4));
+        L.work = o; o += up(sizeof(double) * (2 * size_t(k) + 1) * (size_t(k) + 1));
+        L.coef = o; o += up(sizeof(double) * (size_t(k) + 1));
+        break;
+    case KCT_IRN_TV_CGLS:
+        L.v[0] = o; o += up(size_t(N) * vt);    // r1
+        L.v[1] = o; o += up(size_t(N) * vt);    // q1
+        L.v[2] = o; o += up(size_t(M) * vt);    // p
+        L.v[3] = o; o += up(size_t(M) * vt);    // s
+        L.v[4] = o; o += up(size_t(M) * 4 * 3); // r2 (gradient space, FP32)
+        L.v[5] = o; o += up(size_t(M) * 4);     // L weights
+        break;
+    }
+    L.total = o;
+    return L;
+}
+
+} // namespace
+
+} // namespace kct
+
+using namespace kct;
+
+struct kct_state {
+    kct_plan *plan = nullptr;
+    kct_solve_params prm{};
+    const float *b = nullptr;
+    float *x = nullptr;
+    char *ws = nullptr;
+    double *hist = nullptr;
+    hipStream_t st = nullptr;
+    Layout L;
+    int enqueued = 0;
+    bool started = false;
+    bool finalized = false;
+    int total = 0; // iterations to run (IRN-TV: outer * inner)
+
+    double *S() const { return reinterpret_cast<double *>(ws + L.scal); }
+    double *pa() const { return reinterpret_cast<double *>(ws + L.pa); }
+    double *pb() const { return reinterpret_cast<double *>(ws + L.pb); }
+    double *pc() const { return reinterpret_cast<double *>(ws + L.pc); }
+    double *stage(int i) const { return reinterpret_cast<double *>(ws + L.stage) + 256 * i; }
+    void *pad() const { return ws + L.pad; }
+    void *v(int i) const { return ws + L.v[i]; }
+    int vt() const { return prm.vec_dtype; }
+    int64_t N() const { return plan->n_ray(); }
+    int64_t M() const { return plan->n_vox(); }
+};
+
+namespace {
+
+#define KCT_TRY(expr)                                                                                              \
+    do {                                                                                                           \
+        kct_status s_ = (expr);                                                                                    \
+        if (s_ != KCT_OK) return s_;                                                                               \
+    } while (0)
+
+Reduced red(const kct_state &s, const double *parts, int64_t n, int slot)
+{
+    return reduce_for_scalar(parts, n, s.stage(slot), s.st);
+}
+
+kct_status forward_into(kct_state &s, const void *vol, void *proj, const Epilogue &ep)
+{
+    Plan &p = *s.plan;
+    KCT_TRY(launch_pad_volume(p, vol, s.vt(), s.pad(), s.st));
+    return launch_forward(p, s.pad(), s.vt(), proj, s.vt(), ep, s.st);
+}
+
+// ---------------------------------------------------------------- CGLS
+kct_status cgls_init(kct_state &s)
+{
+    Plan &p = *s.plan;
+    KCT_TRY(vk_fill(s.x, KCT_F32, s.M(), 0.f, s.st));
+    KCT_TRY(vk_scale(s.b, KCT_F32, s.v(0), s.vt(), s.N(), nullptr, -1, nullptr, s.st)); // r = b
+    Epilogue ep;
+    ep.partials = s.pa();
+    KCT_TRY(launch_backward(p, s.v(0), s.vt(), s.v(2), s.vt(), ep, s.st)); // p = A^T r
+    return sk_cgls_init(s.S(), red(s, s.pa(), bwd_num_groups(p), 0), s.prm.lambda, s.prm.n_iter, s.st);
+}
+
+kct_status cgls_iter(kct_state &s)
+{
+    Plan &p = *s.plan;
+    const bool damped = s.prm.lambda != 0.0;
+    Epilogue ef;
+    ef.scal = s.S();
+    ef.partials = s.pa();
+    KCT_TRY(forward_into(s, s.v(2), s.v(1), ef)); // q = A p
+    const Reduced rq = red(s, s.pa(), fwd_num_groups(p), 0);
+    // ||p||^2 comes from the previous volume update; at the first step p = s
+    // and the scalar kernel uses gamma instead.
+    const Reduced rp = (damped && s.enqueued > 0) ? red(s, s.pc(), vk_groups(s.M()), 1) : Reduced{nullptr, 0};
+    KCT_TRY(sk_cgls_alpha(s.S(), rq, rp, s.st));
+    KCT_TRY(vk_axpy_proj(s.v(0), s.v(1), s.vt(), s.N(), s.S(), s.pb(), s.st)); // r -= alpha q
+    Epilogue eb;
+    eb.scal = s.S();
+    eb.coef_idx = S_B0;
+    eb.partials = s.pa();
+    if (damped) {
+        eb.in2 = s.x;
+        eb.in3 = s.v(2);
+    }
+    KCT_TRY(launch_backward(p, s.v(0), s.vt(), s.v(3), s.vt(), eb, s.st)); // s = A^T r - lam^2 x'
+    KCT_TRY(sk_cgls_beta(s.S(), red(s, s.pa(), bwd_num_groups(p), 0), red(s, s.pb(), vk_groups(s.N()), 2),
+                         s.hist, s.st));
+    return vk_cgls_vol(s.x, s.v(2), s.v(3), s.vt(), s.M(), s.S(), s.pc(), s.st);
+}
+
+// ------------------------------------------------------- Golub-Kahan start
+kct_status gk_init(kct_state &s, void *V, double *gk)
+{
+    Plan &p = *s.plan;
+    KCT_TRY(vk_fill(s.x, KCT_F32, s.M(), 0.f, s.st));
+    KCT_TRY(vk_scale(s.b, KCT_F32, s.v(0), s.vt(), s.N(), nullptr, -1, s.pa(), s.st)); // U = b
+    KCT_TRY(sk_gk_init1(s.S(), red(s, s.pa(), vk_groups(s.N()), 0), s.prm.lambda, s.prm.n_iter, s.st));
+    Epilogue eb;
+    eb.scal = s.S();
+    eb.coef_idx = S_B0; // V = A^T U / beta_1
+    eb.partials = s.pa();
+    KCT_TRY(launch_backward(p, s.v(0), s.vt(), V, s.vt(), eb, s.st));
+    return sk_gk_init2(s.S(), red(s, s.pa(), bwd_num_groups(p), 0), gk, s.st);
+}
+
+// One bidiagonalisation step: U from V_in, then V_out from U (in place when equal).
+kct_status gk_step(kct_state &s, void *V_in, void *V_out)
+{
+    Plan &p = *s.plan;
+    Epilogue ef;
+    ef.scal = s.S();
+    ef.coef_idx = S_F0;
+    ef.in1 = s.v(0);
+    ef.partials = s.pa();
+    KCT_TRY(forward_into(s, V_in, s.v(0), ef));
+    KCT_TRY(sk_gk_beta(s.S(), red(s, s.pa(), fwd_num_groups(p), 0), s.st));
+    Epilogue eb;
+    eb.scal = s.S();
+    eb.coef_idx = S_B0;
+    eb.in1 = V_in;
+    eb.partials = s.pa();
+    return launch_backward(p, s.v(0), s.vt(), V_out, s.vt(), eb, s.st);
+}
+
+kct_status lsqr_init(kct_state &s)
+{
+    KCT_TRY(gk_init(s, s.v(1), nullptr));
+    return vk_scale(s.v(1), s.vt(), s.v(2), KCT_F32, s.M(), s.S(), S_V0, nullptr, s.st); // w = V / alpha_1
+}
+
+kct_status lsqr_iter(kct_state &s)
+{
+    KCT_TRY(gk_step(s, s.v(1), s.v(1)));
+    KCT_TRY(sk_lsqr_alpha(s.S(), red(s, s.pa(), bwd_num_groups(*s.plan), 0), s.hist, nullptr, s.st));
+    return vk_lsqr_vol(s.x, static_cast<float *>(s.v(2)), s.v(1), s.vt(), s.M(), s.S(), s.st);
+}
+
+kct_status lsmr_init(kct_state &s)
+{
+    KCT_TRY(gk_init(s, s.v(1), nullptr));
+    KCT_TRY(vk_scale(s.v(1), s.vt(), s.v(2), KCT_F32, s.M(), s.S(), S_V0, nullptr, s.st)); // h = V / alpha_1
+    return vk_fill(s.v(3), KCT_F32, s.M(), 0.f, s.st);                                     // hbar = 0
+}
+
+kct_status lsmr_iter(kct_state &s)
+{
+    KCT_TRY(gk_step(s, s.v(1), s.v(1)));
+    KCT_TRY(sk_lsmr_alpha(s.S(), red(s, s.pa(), bwd_num_groups(*s.plan), 0), s.hist, s.st));
+    return vk_lsmr_vol(s.x, static_cast<float *>(s.v(2)), static_cast<float *>(s.v(3)), s.v(1), s.vt(), s.M(),
+                       s.S(), s.st);
+}
+
+void *basis_slot(kct_state &s, int i)
+{
+    return static_cast<char *>(s.v(1)) + size_t(i) * size_t(s.M()) * dtype_size(s.vt());
+}
+
+double *gk_arr(kct_state &s) { return reinterpret_cast<double *>(s.ws + s.L.gk); }
+
+kct_status hybrid_init(kct_state &s) { return gk_init(s, basis_slot(s, 0), gk_arr(s)); }
+
+kct_status hybrid_iter(kct_state &s)
+{
+    const int k = s.enqueued;
+    KCT_TRY(gk_step(s, basis_slot(s, k), basis_slot(s, k + 1)));
+    return sk_lsqr_alpha(s.S(), red(s, s.pa(), bwd_num_groups(*s.plan), 0), s.hist, gk_arr(s), s.st);
+}
+
+kct_status hybrid_finish(kct_state &s)
+{
+    double *work = reinterpret_cast<double *>(s.ws + s.L.work);
+    double *coef = reinterpret_cast<double *>(s.ws + s.L.coef);
+    KCT_TRY(sk_hybrid_solve(s.S(), gk_arr(s), work, coef, s.st));
+    return vk_combine(s.x, s.v(1), s.vt(), s.M(), coef, s.S(), s.st);
+}
+
+// ---------------------------------------------------------------- IRN-TV
+float *tv_r2(kct_state &s) { return static_cast<float *>(s.v(4)); }
+float *tv_w(kct_state &s) { return static_cast<float *>(s.v(5)); }
+
+kct_status irn_begin_outer(kct_state &s, int outer)
+{
+    Plan &p = *s.plan;
+    const double lam = s.prm.lambda;
+    if (outer == 0) {
+        KCT_TRY(vk_fill(tv_w(s), KCT_F32, s.M(), 1.f, s.st)); // L = I
+    } else {
+        KCT_TRY(tv_weights(p, s.x, tv_w(s), s.prm.tv_eps, s.st));
+    }
+    KCT_TRY(vk_scale(s.b, KCT_F32, s.v(0), s.vt(), s.N(), nullptr, -1, nullptr, s.st)); // r1 = b
+    if (outer > 0) {
+        // r1 = b - A x, r2 = -lam L D x (x is FP32; its padded copy is in vector storage)
+        KCT_TRY(launch_pad_volume_as(p, s.x, KCT_F32, s.vt(), s.pad(), s.st));
+        Epilogue ef;
+        ef.c[0] = -1.0;
+        ef.c[1] = 1.0;
+        ef.in1 = s.v(0);
+        KCT_TRY(launch_forward(p, s.pad(), s.vt(), s.v(0), s.vt(), ef, s.st));
+        KCT_TRY(tv_grad_store(p, s.x, KCT_F32, tv_w(s), tv_r2(s), nullptr, -1, -lam, false, s.st));
+    } else {
+        KCT_TRY(vk_fill(tv_r2(s), KCT_F32, 3 * s.M(), 0.f, s.st));
+    }
+    Epilogue eb;
+    KCT_TRY(launch_backward(p, s.v(0), s.vt(), s.v(3), s.vt(), eb, s.st)); // s = A^T r1
+    KCT_TRY(tv_adjoint_add(p, s.v(3), s.vt(), tv_r2(s), tv_w(s), lam, nullptr, s.pa(), s.st));
+    KCT_TRY(vk_scale(s.v(3), s.vt(), s.v(2), s.vt(), s.M(), nullptr, -1, nullptr, s.st)); // p = s
+    return sk_tv_restart(s.S(), red(s, s.pa(), tv_num_groups(s.M()), 0), outer == 0, s.total, s.st);
+}
+
+kct_status irn_init(kct_state &s)
+{
+    KCT_TRY(vk_fill(s.x, KCT_F32, s.M(), 0.f, s.st));
+    return irn_begin_outer(s, 0);
+}
+
+kct_status irn_iter(kct_state &s)
+{
+    Plan &p = *s.plan;
+    const double lam = s.prm.lambda;
+    Epilogue ef;
+    ef.scal = s.S();
+    ef.partials = s.pa();
+    KCT_TRY(forward_into(s, s.v(2), s.v(1), ef)); // q1 = A p
+    KCT_TRY(tv_grad_norm(p, s.v(2), s.vt(), tv_w(s), lam, s.S(), s.pb(), s.st));
+    KCT_TRY(sk_tv_alpha(s.S(), red(s, s.pa(), fwd_num_groups(p), 0), red(s, s.pb(), tv_num_groups(s.M()), 1), lam,
+                        s.st));
+    KCT_TRY(vk_axpy_proj(s.v(0), s.v(1), s.vt(), s.N(), s.S(), s.pc(), s.st));            // r1 -= alpha q1
+    KCT_TRY(tv_grad_store(p, s.v(2), s.vt(), tv_w(s), tv_r2(s), s.S(), S_V3, 0.0, true, s.st)); // r2
+    Epilogue eb;
+    eb.scal = s.S();
+    KCT_TRY(launch_backward(p, s.v(0), s.vt(), s.v(3), s.vt(), eb, s.st)); // s = A^T r1
+    KCT_TRY(tv_adjoint_add(p, s.v(3), s.vt(), tv_r2(s), tv_w(s), lam, s.S(), s.pa(), s.st));
+    KCT_TRY(sk_cgls_beta(s.S(), red(s, s.pa(), tv_num_groups(s.M()), 0), red(s, s.pc(), vk_groups(s.N()), 2),
+                         s.hist, s.st));
+    KCT_TRY(vk_cgls_vol(s.x, s.v(2), s.v(3), s.vt(), s.M(), s.S(), s.pb(), s.st));
+    const int done = s.enqueued + 1;
+    if (done % s.prm.tv_inner == 0 && done < s.total) KCT_TRY(irn_begin_outer(s, done / s.prm.tv_inner));
+    return KCT_OK;
+}
+
+kct_status enqueue_init(kct_state &s)
+{
+    switch (s.prm.solver) {
+    case KCT_CGLS: return cgls_init(s);
+    case KCT_LSQR: return lsqr_init(s);
+    case KCT_LSMR: return lsmr_init(s);
+    case KCT_HYBRID_LSQR: return hybrid_init(s);
+    case KCT_IRN_TV_CGLS: return irn_init(s);
+    }
+    return fail(KCT_E_INVALID_ARG, "unknown solver");
+}
+
+kct_status enqueue_iter(kct_state &s)
+{
+    switch (s.prm.solver) {
+    case KCT_CGLS: return cgls_iter(s);
+    case KCT_LSQR: return lsqr_iter(s);
+    case KCT_LSMR: return lsmr_iter(s);
+    case KCT_HYBRID_LSQR: return hybrid_iter(s);
+    case KCT_IRN_TV_CGLS: return irn_iter(s);
+    }
+    return fail(KCT_E_INVALID_ARG, "unknown solver");
+}
+
+struct DevGuard {
+    int prev = -1;
+    explicit DevGuard(int d)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        (void)hipSetDevice(d);
+    }
+    ~DevGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+} // namespace
+
+extern "C" {
+
+kct_status kct_solve_workspace_bytes(const kct_plan *plan, const kct_solve_params *params, size_t *bytes)
+{
+    if (!plan || !bytes) return fail(KCT_E_INVALID_ARG, "NULL argument");
+    KCT_TRY(check_params(params));
+    *bytes = layout(*plan, *params).total;
+    return KCT_OK;
+}
+
+kct_status kct_state_create(kct_plan *plan, const kct_solve_params *params, const void *d_b, void *d_x,
+                            void *d_ws, size_t ws_bytes, double *d_history, void *stream, kct_state **out)
+{
+    if (!out) return fail(KCT_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!plan || !d_b || !d_x || !d_ws) return fail(KCT_E_INVALID_ARG, "NULL argument");
+    KCT_TRY(check_params(params));
+    const Layout L = layout(*plan, *params);
+    if (ws_bytes < L.total) return fail(KCT_E_BUDGET, "workspace smaller than kct_solve_workspace_bytes");
+    if (reinterpret_cast<uintptr_t>(d_ws) % ALIGN) return fail(KCT_E_INVALID_ARG, "workspace must be 256-byte aligned");
+    kct_state *s = new (std::nothrow) kct_state();
+    if (!s) return fail(KCT_E_OOM, "host allocation failed");
+    s->plan = plan;
+    s->prm = *params;
+    s->b = static_cast<const float *>(d_b);
+    s->x = static_cast<float *>(d_x);
+    s->ws = static_cast<char *>(d_ws);
+    s->hist = d_history;
+    s->st = static_cast<hipStream_t>(stream);
+    s->L = L;
+    s->total = params->solver == KCT_IRN_TV_CGLS ? params->tv_outer * params->tv_inner : params->n_iter;
+    *out = s;
+    return KCT_OK;
+}
+
+kct_status kct_state_step(kct_state *s, int32_t n_steps)
+{
+    if (!s || n_steps < 0) return fail(KCT_E_INVALID_ARG, "bad state or step count");
+    DevGuard dg(s->plan->device);
+    if (!s->started) {
+        KCT_TRY(enqueue_init(*s));
+        s->started = true;
+    }
+    for (int i = 0; i < n_steps && s->enqueued < s->total; ++i) {
+        KCT_TRY(enqueue_iter(*s));
+        ++s->enqueued;
+    }
+    if (s->enqueued == s->total && !s->finalized) {
+        if (s->prm.solver == KCT_HYBRID_LSQR) KCT_TRY(hybrid_finish(*s));
+        s->finalized = true;
+    }
+    return KCT_OK;
+}
+
+kct_status kct_state_progress(const kct_state *s, int32_t *iters, int32_t *finished)
+{
+    if (!s) return fail(KCT_E_INVALID_ARG, "state is NULL");
+    if (iters) *iters = s->enqueued;
+    if (finished) *finished = s->finalized ? 1 : 0;
+    return KCT_OK;
+}
+
+kct_status kct_state_destroy(kct_state *s)
+{
+    delete s;
+    return KCT_OK;
+}
+
+kct_status kct_solve(kct_plan *plan, const kct_solve_params *params, const void *d_b, void *d_x, void *d_ws,
+                     size_t ws_bytes, double *d_history, void *stream)
+{
+    kct_state *s = nullptr;
+    KCT_TRY(kct_state_create(plan, params, d_b, d_x, d_ws, ws_bytes, d_history, stream, &s));
+    const kct_status r = kct_state_step(s, s->total);
+    kct_state_destroy(s);
+    return r;
+}
+
+} // extern "C"

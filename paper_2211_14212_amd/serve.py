@@ -1,0 +1,248 @@
+"""Continuous-batching reconstruction server.
+
+Requests (a geometry, measured projections b, a solver and an iteration
+count) arrive over time.  The server admits them in arrival order while the
+HBM they need (plan tables, workspace, b, x, history) fits a byte budget,
+gives each admitted request its own HIP stream and device-resident Krylov
+state (kct_state), and advances all active requests one iteration at a time,
+so kernels of different requests overlap on the GPU.  A request leaves when
+its last iteration has run on the device; its memory is freed and queued
+requests are admitted in its place.  Each request's result is bitwise the
+same as a solo kct_solve of it (deterministic kernels, private buffers).
+
+Latency = completion time - arrival time.  The serial baseline runs the same
+stream through the plain per-request path (one kct_solve at a time, FIFO).
+
+CLI:  python -m paper_2211_14212_amd.serve [--requests 64] [--rate 2.0]
+          [--size-scale 1.0] [--budget-gb 200] [--serial]
+"""
+from __future__ import annotations
+
+import argparse
+import dataclasses
+import json
+import math
+import sys
+import time
+from collections import deque
+
+import numpy as np
+import torch
+
+from . import Geometry, Plan
+
+
+@dataclasses.dataclass
+class Request:
+    id: int
+    arrival: float          # seconds after the stream starts
+    geom: Geometry
+    b: torch.Tensor         # FP32 projections on the server's device
+    solver: str = "cgls"
+    n_iter: int = 20
+    lam: float = 0.0
+    vec_dtype: torch.dtype = torch.float32
+
+
+@dataclasses.dataclass
+class Result:
+    id: int
+    arrival: float
+    admitted: float
+    finished: float
+    x: torch.Tensor | None
+    history: torch.Tensor | None
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+class _Active:
+    def __init__(self, req: Request, plan: Plan, state, stream, nbytes: int, admitted: float):
+        self.req, self.plan, self.state, self.stream = req, plan, state, stream
+        self.nbytes, self.admitted = nbytes, admitted
+        self.event = None
+        self.enqueued = 0
+
+
+def request_bytes(plan: Plan, req: Request) -> int:
+    """Device bytes a request holds while active."""
+    ws = plan.workspace_bytes(req.solver, req.n_iter, req.lam, req.vec_dtype)
+    x = req.geom.n_voxels * 4
+    hist = max(req.n_iter, 1) * 4 * 8
+    return ws + x + hist + plan.device_bytes()
+
+
+class Server:
+    def __init__(self, budget_bytes: float = 200e9, device: int = 0, max_active: int = 16,
+                 keep_results: bool = True):
+        self.budget = int(budget_bytes)
+        self.device = torch.device("cuda", device)
+        self.max_active = max_active
+        self.keep_results = keep_results
+        self.log = []
+
+    def run(self, requests: list[Request]) -> list[Result]:
+        """Serve `requests` (sorted by arrival) in real time; returns results by id."""
+        pending = deque(sorted(requests, key=lambda r: r.arrival))
+        queue: deque[Request] = deque()
+        active: list[_Active] = []
+        used = 0
+        results: dict[int, Result] = {}
+        t0 = time.perf_counter()
+        with torch.cuda.device(self.device):
+            while pending or queue or active:
+                now = time.perf_counter() - t0
+                while pending and pending[0].arrival <= now:
+                    queue.append(pending.popleft())
+                # Admission: FIFO while the head fits the budget.
+                while queue and len(active) < self.max_active:
+                    req = queue[0]
+                    plan = Plan(req.geom, self.device.index)
+                    need = request_bytes(plan, req)
+                    if used + need > self.budget and active:
+                        plan.close()
+                        break
+                    queue.popleft()
+                    stream = torch.cuda.Stream(device=self.device)
+                    state = plan.state(req.b, req.solver, req.n_iter, req.lam, req.vec_dtype, stream=stream)
+                    used += need
+                    a = _Active(req, plan, state, stream, need, time.perf_counter() - t0)
+                    active.append(a)
+                    self.log.append(("admit", req.id, a.admitted, used))
+                # Advance every active request whose previous step has finished.
+                progressed = False
+                for a in active:
+                    if a.enqueued < a.req.n_iter and (a.event is None or a.event.query()):
+                        a.state.step(1)
+                        a.enqueued += 1
+                        a.event = torch.cuda.Event()
+                        a.event.record(a.stream)
+                        progressed = True
+                    elif a.enqueued == 0 and a.req.n_iter == 0:
+                        a.state.step(0)
+                        a.event = torch.cuda.Event()
+                        a.event.record(a.stream)
+                        a.enqueued = -1
+                # Retire requests whose last iteration has completed.
+                still = []
+                for a in active:
+                    done_enq = a.enqueued == a.req.n_iter or a.enqueued == -1
+                    if done_enq and a.event is not None and a.event.query():
+                        fin = time.perf_counter() - t0
+                        x = a.state.x if self.keep_results else None
+                        h = a.state.history if self.keep_results else None
+                        results[a.req.id] = Result(a.req.id, a.req.arrival, a.admitted, fin, x, h)
+                        a.state.close()
+                        a.plan.close()
+                        used -= a.nbytes
+                        self.log.append(("finish", a.req.id, fin, used))
+                    else:
+                        still.append(a)
+                active = still
+                if not progressed:
+                    if not active and not queue and pending:
+                        time.sleep(max(0.0, min(0.01, pending[0].arrival - (time.perf_counter() - t0))))
+                    else:
+                        time.sleep(0.0002)
+        return [results[r.id] for r in sorted(requests, key=lambda r: r.id)]
+
+
+def serve_serial(requests: list[Request], device: int = 0, keep_results: bool = True) -> list[Result]:
+    """Plain per-request path: each request solved alone with kct_solve in
+    arrival order; latency includes waiting behind earlier requests."""
+    dev = torch.device("cuda", device)
+    out = {}
+    t0 = time.perf_counter()
+    with torch.cuda.device(dev):
+        for req in sorted(requests, key=lambda r: r.arrival):
+            now = time.perf_counter() - t0
+            if req.arrival > now:
+                time.sleep(req.arrival - now)
+            start = time.perf_counter() - t0
+            plan = Plan(req.geom, device)
+            x, h = plan.solve(req.b, req.solver, req.n_iter, req.lam, req.vec_dtype)
+            torch.cuda.synchronize()
+            fin = time.perf_counter() - t0
+            out[req.id] = Result(req.id, req.arrival, start, fin, x if keep_results else None,
+                                 h if keep_results else None)
+            plan.close()
+    return [out[r.id] for r in sorted(requests, key=lambda r: r.id)]
+
+
+def percentile(values, q):
+    """Nearest-rank percentile."""
+    v = sorted(values)
+    if not v:
+        return float("nan")
+    k = max(1, int(math.ceil(q / 100.0 * len(v))))
+    return v[k - 1]
+
+
+def summarize(results: list[Result]) -> dict:
+    lat = [r.latency for r in results]
+    makespan = max(r.finished for r in results) - min(r.arrival for r in results)
+    return {"n": len(results), "p50_s": percentile(lat, 50), "p99_s": percentile(lat, 99),
+            "mean_s": float(np.mean(lat)), "throughput_req_per_s": len(results) / makespan,
+            "makespan_s": makespan}
+
+
+def make_requests(n=64, rate=2.0, seed=5, size_scale=1.0, device=0, det_scale=None, angle_scale=None):
+    """The seeded request stream of synth.serve_stream, with projections of a
+    random ellipsoid phantom (GPU forward projection, Poisson noise I0 = 1e5)."""
+    import synth
+
+    dev = torch.device("cuda", device)
+    det_scale = size_scale if det_scale is None else det_scale
+    angle_scale = size_scale if angle_scale is None else angle_scale
+    reqs = []
+    for r in synth.serve_stream(n, rate, seed):
+        g = dict(r["geom"])
+        n_vox = max(8, int(round(g["nx"] * size_scale)))
+        side = max(8, 2 * int(round(g["nu"] * det_scale / 2)))
+        na = max(4, int(round(g["n_angles"] * angle_scale)))
+        pitch = 1.1 * n_vox * 0.5 * (g["dsd"] / g["dso"]) / side
+        g.update(nx=n_vox, ny=n_vox, nz=n_vox, nu=side, nv=side, du=pitch, dv=pitch, n_angles=na)
+        gd = synth.geometry(g)
+        geom = Geometry.from_dict(gd)
+        xt = synth.ellipsoid_phantom(gd, r["n_ellipsoids"], (2.0, 12.0 * n_vox / 128), (0.01, 0.05), r["seed"])
+        plan = Plan(geom, device)
+        b = plan.forward(torch.from_numpy(xt).to(dev))
+        gen = torch.Generator(device=dev).manual_seed(r["seed"])
+        counts = torch.poisson(1e5 * torch.exp(-b), generator=gen).clamp_(min=1.0)
+        b = torch.log(1e5 / counts).float().contiguous()
+        plan.close()
+        reqs.append(Request(r["id"], r["arrival"], geom, b, r["solver"], r["n_iter"]))
+    torch.cuda.synchronize()
+    return reqs
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description="continuous-batching server vs serial per-request path")
+    ap.add_argument("--requests", type=int, default=64)
+    ap.add_argument("--rate", type=float, default=2.0)
+    ap.add_argument("--size-scale", type=float, default=1.0)
+    ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--max-active", type=int, default=16)
+    ap.add_argument("--no-serial", action="store_true")
+    args = ap.parse_args(argv)
+    print("[serve] generating requests", file=sys.stderr, flush=True)
+    reqs = make_requests(args.requests, args.rate, size_scale=args.size_scale)
+    work = sum(r.n_iter * r.geom.n_rays for r in reqs)
+    print(f"[serve] {len(reqs)} requests, {work / 1e9:.1f} G ray-iterations", file=sys.stderr, flush=True)
+    srv = Server(args.budget_gb * 1e9, max_active=args.max_active, keep_results=False)
+    res = srv.run(reqs)
+    out = {"batched": summarize(res)}
+    print(f"[serve] batched {out['batched']}", file=sys.stderr, flush=True)
+    if not args.no_serial:
+        ser = serve_serial(reqs, keep_results=False)
+        out["serial"] = summarize(ser)
+        print(f"[serve] serial {out['serial']}", file=sys.stderr, flush=True)
+    out["config"] = {"requests": args.requests, "rate_per_s": args.rate, "size_scale": args.size_scale,
+                     "budget_gb": args.budget_gb, "max_active": args.max_active}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,165 @@
+"""GPU solver parity: CGLS, LSQR, LSMR (damped and not) and hybrid LSQR from
+the HIP library against the FP64 oracle on the same seeded FP32 inputs.
+
+Gate: relative L2 of x_k <= 1e-5 (FP32 vectors, FP64 scalars, FP64 ray
+geometry).  The intrinsic sensitivity of the workloads was measured with the
+oracle (every matvec output rounded to FP32): about 1e-7 for the 32^3 CGLS-20
+workload, so the gate leaves two orders of margin.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from oracle import solvers as S
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda", 0)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def kct(gpu_lib):
+    return gpu_lib
+
+
+def _problem(name):
+    """(oracle geometry, kct geometry, FP32 b) for a workload or reduced copy."""
+    if name == "cgls32":
+        gd = synth.geometry("cgls32")
+        og = oracle.Geometry.from_dict(gd)
+        xt = synth.phantom("cgls32")
+        b, _ = synth.add_noise(oracle.forward(og, xt), synth.WORKLOADS["cgls32"]["noise"], 1)
+    elif name == "medical48":
+        gd = synth.crop_geometry("medical256", 48, 96, 40)
+        og = oracle.Geometry.from_dict(gd)
+        xt = synth.ellipsoid_phantom(gd, 12, (1.0, 6.0), (0.1, 1.0), 2)
+        b, _ = synth.add_noise(oracle.forward(og, xt), dict(kind="poisson", i0=1e5), 2)
+    elif name == "torso40":
+        gd = synth.geometry(dict(nx=40, ny=40, nz=32, vx=0.5, vy=0.5, vz=0.5, nu=80, nv=60, du=0.4, dv=0.4,
+                                 dso=1000.0, dsd=1500.0, n_angles=36))
+        og = oracle.Geometry.from_dict(gd)
+        xt = synth.torso_phantom(gd, 12, (0.15, 0.5), 0.2, 2, 2.0, 3)
+        b, _ = synth.add_noise(oracle.forward(og, xt), dict(kind="poisson", i0=1e5), 3)
+    else:
+        raise KeyError(name)
+    import paper_2211_14212_amd as kct
+
+    return og, kct.Geometry.from_dict(gd), b.astype(np.float32)
+
+
+def _oracle_ops(og):
+    return (lambda v: oracle.forward(og, v)), (lambda y: oracle.adjoint(og, y))
+
+
+CASES = [
+    ("cgls32", "cgls", 20, 0.0),
+    ("cgls32", "lsqr", 20, 0.0),
+    ("cgls32", "lsmr", 20, 0.0),
+    ("medical48", "cgls", 30, 0.0),
+    ("medical48", "lsqr", 30, 0.0),
+    ("medical48", "lsmr", 30, 0.0),
+    ("torso40", "lsqr", 30, 10.0),
+    ("torso40", "lsmr", 30, 10.0),
+    ("torso40", "cgls", 30, 10.0),
+]
+
+
+@pytest.mark.parametrize("name,solver,n_iter,lam", CASES)
+def test_solver_matches_oracle(kct, name, solver, n_iter, lam):
+    og, kg, b = _problem(name)
+    print(f"[solve] {name} {solver} k={n_iter} lam={lam}", flush=True)
+    plan = kct.Plan(kg)
+    x, hist = plan.solve(torch.from_numpy(b).to(DEV), solver, n_iter, lam)
+    torch.cuda.synchronize()
+    A, AT = _oracle_ops(og)
+    ref, rh = getattr(S, solver)(A, AT, b.astype(np.float64), n_iter, lam)
+    got = x.cpu().numpy().astype(np.float64)
+    assert _rel(got, ref) <= 1e-5
+    h = hist.cpu().numpy()
+    key = {"cgls": "res", "lsqr": "res", "lsmr": "normal"}[solver]
+    np.testing.assert_allclose(h[:, 0], rh[key], rtol=1e-5)
+    np.testing.assert_allclose(h[:, 1], rh["alpha"], rtol=1e-5)
+    np.testing.assert_allclose(h[:, 2], rh["beta"], rtol=1e-5)
+    assert np.all(h[:, 3] == 0)
+
+
+def test_hybrid_lsqr_matches_oracle_and_damped_lsqr(kct):
+    og, kg, b = _problem("torso40")
+    plan = kct.Plan(kg)
+    bt = torch.from_numpy(b).to(DEV)
+    lam, k = 10.0, 25
+    xh, hh = plan.solve(bt, "hybrid_lsqr", k, lam)
+    xd, hd = plan.solve(bt, "lsqr", k, lam)
+    torch.cuda.synchronize()
+    A, AT = _oracle_ops(og)
+    ref, _ = S.hybrid_lsqr(A, AT, b.astype(np.float64), k, lam)
+    assert _rel(xh.cpu().numpy(), ref) <= 1e-5
+    # Hybrid LSQR with a fixed lambda equals damped LSQR (Sec. 2.2.1).
+    assert _rel(xh.cpu().numpy(), xd.cpu().numpy()) <= 1e-5
+    np.testing.assert_allclose(hh.cpu().numpy()[:, 0], hd.cpu().numpy()[:, 0], rtol=1e-6)
+
+
+def test_cgls_equals_lsqr_on_gpu(kct):
+    og, kg, b = _problem("cgls32")
+    plan = kct.Plan(kg)
+    bt = torch.from_numpy(b).to(DEV)
+    xc, _ = plan.solve(bt, "cgls", 15)
+    xq, _ = plan.solve(bt, "lsqr", 15)
+    assert _rel(xc.cpu().numpy(), xq.cpu().numpy()) <= 1e-5
+
+
+def test_breakdown_b_zero(kct):
+    og, kg, b = _problem("cgls32")
+    plan = kct.Plan(kg)
+    z = torch.zeros(kg.proj_shape, device=DEV)
+    for solver in ("cgls", "lsqr", "lsmr", "hybrid_lsqr"):
+        x, h = plan.solve(z, solver, 5, 0.0)
+        torch.cuda.synchronize()
+        assert torch.all(x == 0), solver
+        assert torch.all(torch.isfinite(h)), solver
+        assert torch.all(h[:, 3] == 1), solver
+
+
+def test_nonfinite_b_flagged(kct):
+    og, kg, b = _problem("cgls32")
+    plan = kct.Plan(kg)
+    bn = torch.from_numpy(b).to(DEV)
+    bn[0, 10, 10] = float("nan")
+    for solver in ("cgls", "lsqr", "lsmr"):
+        x, h = plan.solve(bn, solver, 4, 0.0)
+        torch.cuda.synchronize()
+        assert torch.all(h[:, 3] == 2), solver
+        assert torch.all(x == 0), solver
+
+
+def test_state_resume_equals_straight_run(kct):
+    og, kg, b = _problem("cgls32")
+    plan = kct.Plan(kg)
+    bt = torch.from_numpy(b).to(DEV)
+    for solver in ("cgls", "lsqr", "lsmr", "hybrid_lsqr"):
+        st = plan.state(bt, solver, 12, 0.5)
+        st.step(5)
+        st.step(0)
+        st.step(7)
+        assert st.progress() == (12, True)
+        x2, h2 = plan.solve(bt, solver, 12, 0.5)
+        torch.cuda.synchronize()
+        assert torch.equal(st.x, x2), solver
+        assert torch.equal(st.history, h2), solver
+        st.close()
+
+
+def test_solve_bitwise_deterministic(kct):
+    og, kg, b = _problem("medical48")
+    plan = kct.Plan(kg)
+    bt = torch.from_numpy(b).to(DEV)
+    x1, h1 = plan.solve(bt, "lsmr", 10)
+    x2, h2 = plan.solve(bt, "lsmr", 10)
+    torch.cuda.synchronize()
+    assert torch.equal(x1, x2) and torch.equal(h1, h2)

@@ -158,3 +158,13 @@ def test_forward_rays_subset():
     full = oracle.forward(g, x).ravel()
     rays = np.random.default_rng(2).choice(full.size, 500, replace=False)
     np.testing.assert_array_equal(oracle.forward_rays(g, x, rays), full[rays])
+
+
+def test_count_nnz_matches_dense():
+    for g in _tiny_geoms():
+        A = dense.system_matrix(g)
+        nnz, hits = oracle.count_nnz(g)
+        # Segments of positive length == positive entries of the brute-force A
+        # (grazing segments of ~1e-15 mm included on both sides).
+        assert nnz == int((A > 0).sum())
+        assert hits == int((A.sum(1) > 0).sum())
