@@ -116,15 +116,15 @@ def _cpu_model():
     return "unknown"
 
 
-def traffic_entry(kernel_key, digest, launches_bytes_alg):
-    """HBM bytes per launch from committed rocprofv3 counter summaries, if they
-    were taken on the current kernel source; else None."""
+def traffic_entry(kernel_key, digest):
+    """HBM bytes per launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), if it was taken on
+    the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", f"{WORKLOAD}_counters.json")
     if not os.path.exists(path):
         return None
-    d = json.load(open(path))
-    k = d.get("kernels", {}).get(kernel_key)
-    if not k or d.get("src_digest") != digest:
+    k = json.load(open(path)).get("kernels", {}).get(kernel_key)
+    if not k or k.get("src_digest") != digest:
         return None
     return k.get("hbm_bytes_per_launch")
 
@@ -137,6 +137,9 @@ def main():
     ap.add_argument("--reps", type=int, default=5, help="calls per projector timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solves", action="store_true")
+    ap.add_argument("--profile-kernels", action="store_true",
+                    help="only run the projectors (and a plain 1 GiB copy for counter calibration) "
+                         "a few times, for rocprofv3; prints no JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU angle-sharded "
@@ -159,6 +162,18 @@ def main():
     x_true = synth.phantom(WORKLOAD)
     plan = kct.Plan(kg)
     xt = torch.from_numpy(x_true).to(dev)
+    if args.profile_kernels:
+        y = torch.empty(kg.proj_shape, device=dev)
+        xb = torch.empty(kg.vol_shape, device=dev)
+        src = torch.ones(1 << 28, device=dev)  # 1 GiB of FP32
+        dst = torch.empty_like(src)
+        for _ in range(args.reps):
+            plan.forward(xt, out=y)
+            plan.backproject(y, out=xb)
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[bench] profile-kernels done")
+        return
     log("[bench] clean projections (GPU forward) + Poisson noise")
     b_clean = plan.forward(xt).cpu().numpy()
     b_np, noise_info = synth.add_noise(b_clean, synth.WORKLOADS[WORKLOAD]["noise"], synth.WORKLOADS[WORKLOAD]["seed"])
@@ -209,7 +224,7 @@ def main():
         kname, ms, alg = "backward", bwd_ms, nnz * 4 + M * 4
         digest = src_digest("proj_bwd.hip")
     achieved = alg / (ms / 1000.0) / 1e9
-    traffic = traffic_entry(kname, digest, alg)
+    traffic = traffic_entry(kname, digest)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
                 "launch_ms": round(ms, 3), "algorithmic_bytes_per_launch": alg}

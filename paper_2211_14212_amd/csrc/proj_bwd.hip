@@ -140,6 +140,9 @@ __global__ __launch_bounds__(256) void k_backward(const TP *__restrict__ proj, T
             cinv[2 * c + 1] = dym != 0.0 ? 1.0 / dym : 0.0;
         }
         for (int r = threadIdx.x; r < ph; r += 256) rinv[r] = invv[iv_lo + r];
+        // The unrolled column loop reads up to NCM-1 values past the patch;
+        // they are multiplied by a zero length, so they must be finite.
+        if (threadIdx.x < NCM) patch[pw * ph + threadIdx.x] = 0.f;
         __syncthreads();
 
         if (valid) {
