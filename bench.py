@@ -31,7 +31,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GRays/s fwd proj, GVoxel-views/s backproj; CGLS it/s; p50/p99 recon latency"
 WORKLOAD = "medical256"
+DTYPES = {"f32": "float32", "bf16": "bfloat16", "f16": "float16"}
 HBM_PEAK_GBS = 8000.0
+VALU_PEAK_GINSTS = 256 * 2.4  # 256 CUs x 2.4 GHz x one wave64 VALU instruction per CU-clock
 
 
 def log(*a):
@@ -60,9 +62,9 @@ def timed(fn, reps, torch):
     return e0.elapsed_time(e1) / reps
 
 
-def iter_rate(plan, b, solver, warmup, steps, torch):
+def iter_rate(plan, b, solver, warmup, steps, torch, vec_dtype=None):
     """Iterations/s of `solver` over `steps` iterations after `warmup` ones."""
-    st = plan.state(b, solver, warmup + steps)
+    st = plan.state(b, solver, warmup + steps, vec_dtype=vec_dtype or torch.float32)
     st.step(warmup)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -116,17 +118,19 @@ def _cpu_model():
     return "unknown"
 
 
-def traffic_entry(kernel_key, digest):
-    """HBM bytes per launch from the committed rocprofv3 counter summary
-    (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), if it was taken on
-    the current kernel source; else None."""
+def counter_entry(kernel_key, digest):
+    """The committed rocprofv3 counter summary of one projector kernel, if it
+    was taken on the current kernel source; else None.  It holds the HBM bytes
+    per launch (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), the L2
+    hit rate (TCC_HIT / (TCC_HIT + TCC_MISS)) and the VALU instructions per
+    unit of work (SQ_INSTS_VALU over nonzeros or voxel-views)."""
     path = os.path.join(ROOT, "profiles", f"{WORKLOAD}_counters.json")
     if not os.path.exists(path):
         return None
     k = json.load(open(path)).get("kernels", {}).get(kernel_key)
     if not k or k.get("src_digest") != digest:
         return None
-    return k.get("hbm_bytes_per_launch")
+    return k
 
 
 def main():
@@ -137,6 +141,12 @@ def main():
     ap.add_argument("--reps", type=int, default=5, help="calls per projector timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solves", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--workload", default=WORKLOAD, help="synthetic workload (default: the benchmark's)")
+    ap.add_argument("--vec-dtype", default="f32", choices=sorted(DTYPES),
+                    help="storage of the projector-facing Krylov vectors")
+    ap.add_argument("--serve-requests", type=int, default=16)
+    ap.add_argument("--serve-scale", type=float, default=0.25)
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only run the projectors (and a plain 1 GiB copy for counter calibration) "
                          "a few times, for rocprofv3; prints no JSON line")
@@ -154,12 +164,17 @@ def main():
 
     kct.require_gpu()
     dev = torch.device("cuda", 0)
-    gd = synth.geometry(WORKLOAD)
+    wl = args.workload
+    vdt = getattr(torch, DTYPES[args.vec_dtype])
+    gd = synth.geometry(wl)
     kg = kct.Geometry.from_dict(gd)
-    stats = json.load(open(os.path.join(ROOT, "tests", "golden", "workload_stats.json")))[WORKLOAD]
+    stats = json.load(open(os.path.join(ROOT, "tests", "golden", "workload_stats.json"))).get(wl)
+    if stats is None:  # no exact count stored: sizes only, nnz unknown
+        stats = {"rays": kg.n_rays, "voxels": kg.n_voxels, "voxel_views": kg.n_voxels * len(kg.angles),
+                 "nnz": None, "hit_rays": None}
 
-    log("[bench] phantom")
-    x_true = synth.phantom(WORKLOAD)
+    log(f"[bench] phantom ({wl})")
+    x_true = synth.phantom(wl)
     plan = kct.Plan(kg)
     xt = torch.from_numpy(x_true).to(dev)
     if args.profile_kernels:
@@ -174,30 +189,37 @@ def main():
         torch.cuda.synchronize()
         log("[bench] profile-kernels done")
         return
-    log("[bench] clean projections (GPU forward) + Poisson noise")
-    b_clean = plan.forward(xt).cpu().numpy()
-    b_np, noise_info = synth.add_noise(b_clean, synth.WORKLOADS[WORKLOAD]["noise"], synth.WORKLOADS[WORKLOAD]["seed"])
-    del b_clean
-    b = torch.from_numpy(b_np).to(dev)
+    log("[bench] clean projections (GPU forward) + noise")
+    if wl == WORKLOAD:
+        b_clean = plan.forward(xt).cpu().numpy()
+        b_np, noise_info = synth.add_noise(b_clean, synth.WORKLOADS[wl]["noise"], synth.WORKLOADS[wl]["seed"])
+        del b_clean
+        b = torch.from_numpy(b_np).to(dev)
+        del b_np
+    else:
+        b, noise_info = synth.add_noise_torch(plan.forward(xt), synth.WORKLOADS[wl]["noise"],
+                                              synth.WORKLOADS[wl]["seed"])
     torch.cuda.synchronize()
 
     # ---- the step: one CGLS iteration ------------------------------------
     log("[bench] CGLS iterations")
-    cgls_rate, cgls_ms, _ = iter_rate(plan, b, "cgls", args.warmup, args.steps, torch)
+    cgls_rate, cgls_ms, _ = iter_rate(plan, b, "cgls", args.warmup, args.steps, torch, vdt)
     log(f"[bench] CGLS {cgls_rate:.2f} it/s")
 
     # ---- operators ---------------------------------------------------------
     log("[bench] projector timings")
-    y_out = torch.empty(kg.proj_shape, device=dev)
-    x_out = torch.empty(kg.vol_shape, device=dev)
-    fwd_ms = timed(lambda: plan.forward(xt, out=y_out), args.reps, torch)
-    bwd_ms = timed(lambda: plan.backproject(b, out=x_out), args.reps, torch)
+    y_out = torch.empty(kg.proj_shape, device=dev, dtype=vdt)
+    x_out = torch.empty(kg.vol_shape, device=dev, dtype=vdt)
+    x_in, b_in = xt.to(vdt), b.to(vdt)
+    fwd_ms = timed(lambda: plan.forward(x_in, out=y_out), args.reps, torch)
+    bwd_ms = timed(lambda: plan.backproject(b_in, out=x_out), args.reps, torch)
+    del x_in, b_in
     n_rays, n_vv, nnz = stats["rays"], stats["voxel_views"], stats["nnz"]
     M, N = stats["voxels"], stats["rays"]
     log(f"[bench] fwd {fwd_ms:.2f} ms  bwd {bwd_ms:.2f} ms")
 
-    lsqr_rate, _, _ = iter_rate(plan, b, "lsqr", args.warmup, args.steps, torch)
-    lsmr_rate, _, _ = iter_rate(plan, b, "lsmr", args.warmup, args.steps, torch)
+    lsqr_rate, _, _ = iter_rate(plan, b, "lsqr", args.warmup, args.steps, torch, vdt)
+    lsmr_rate, _, _ = iter_rate(plan, b, "lsmr", args.warmup, args.steps, torch, vdt)
     log(f"[bench] LSQR {lsqr_rate:.2f} it/s  LSMR {lsmr_rate:.2f} it/s")
 
     solves = {}
@@ -205,7 +227,7 @@ def main():
         for solver in ("cgls", "lsqr", "lsmr"):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            xs, hs = plan.solve(b, solver, 30)
+            xs, hs = plan.solve(b, solver, 30, vec_dtype=vdt)
             torch.cuda.synchronize()
             solves[f"{solver}30_s"] = round(time.perf_counter() - t0, 4)
             h = hs.cpu().numpy()
@@ -216,21 +238,52 @@ def main():
 
     # ---- roofline of the dominant kernel ----------------------------------
     # Algorithmic bytes of a matrix-free sparse matvec: every nonzero a_ij
-    # reads one input value, every output is written once (FP32).
-    if fwd_ms >= bwd_ms:
-        kname, ms, alg = "forward", fwd_ms, nnz * 4 + N * 4
-        digest = src_digest("proj_fwd.hip")
-    else:
-        kname, ms, alg = "backward", bwd_ms, nnz * 4 + M * 4
-        digest = src_digest("proj_bwd.hip")
-    achieved = alg / (ms / 1000.0) / 1e9
-    traffic = traffic_entry(kname, digest)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
-                "launch_ms": round(ms, 3), "algorithmic_bytes_per_launch": alg}
+    # reads one input value, every output is written once.
+    es = torch.tensor([], dtype=vdt).element_size()
+    roofline = None
+    if nnz is not None:
+        if fwd_ms >= bwd_ms:
+            kname, ms, alg = "forward", fwd_ms, nnz * es + N * es
+            digest = src_digest("proj_fwd.hip")
+        else:
+            kname, ms, alg = "backward", bwd_ms, nnz * es + M * es
+            digest = src_digest("proj_bwd.hip")
+        achieved = alg / (ms / 1000.0) / 1e9
+        ce = counter_entry(kname, digest) if wl == WORKLOAD and es == 4 else None
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": ce.get("hbm_bytes_per_launch") if ce else None, "kernel": kname,
+                    "launch_ms": round(ms, 3), "algorithmic_bytes_per_launch": alg}
+        if ce and "valu_insts_per_unit" in ce:
+            # The issue ceiling the gathers really meet: one wave64 VALU
+            # instruction per CU per clock (4 SIMDs, 4 cycles each).
+            units = nnz if kname == "forward" else M * len(kg.angles)
+            rate = ce["valu_insts_per_unit"] * units / (ms / 1000.0)
+            roofline["l2_hit"] = round(ce["l2_hit"], 4) if "l2_hit" in ce else None
+            roofline["valu"] = {"insts_per_unit": round(ce["valu_insts_per_unit"], 4), "unit": ce["unit"],
+                                "achieved": round(rate / 1e9, 1), "peak": VALU_PEAK_GINSTS,
+                                "unit_rate": "G wave-instructions/s", "frac": round(rate / 1e9 / VALU_PEAK_GINSTS, 4)}
+
+    serving = None
+    if not args.no_serve and wl == WORKLOAD:
+        # Latency of the request mix (seeded stream, 2 req/s, shrunk by
+        # --serve-scale in volume side, detector side and angle count):
+        # continuous batching against serial per-request solves.
+        from paper_2211_14212_amd import serve
+
+        log("[bench] serving stream")
+        del y_out, x_out
+        torch.cuda.empty_cache()
+        reqs = serve.make_requests(args.serve_requests, 2.0, seed=5, size_scale=args.serve_scale)
+        batched = serve.summarize(serve.Server(200e9, keep_results=False).run(reqs))
+        serial = serve.summarize(serve.serve_serial(reqs, keep_results=False))
+        serving = {"requests": args.serve_requests, "rate_per_s": 2.0, "size_scale": args.serve_scale,
+                   "batched": {k: round(v, 4) for k, v in batched.items()},
+                   "serial": {k: round(v, 4) for k, v in serial.items()}}
+        log(f"[bench] serving {serving}")
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and wl == WORKLOAD:
         log("[bench] cpu baseline (oracle)")
         cpu = cpu_baseline(gd, x_true)
         log(f"[bench] cpu {cpu['value']:.4f} it/s on {cpu['cores']} threads")
@@ -239,17 +292,19 @@ def main():
         "metric": METRIC, "value": round(cgls_rate, 3), "unit": "CGLS it/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(cgls_ms / args.steps, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": WORKLOAD, "volume": [gd["nx"], gd["ny"], gd["nz"]], "voxel_mm": gd["vx"],
+        "config": {"workload": wl, "vec_storage": args.vec_dtype, "volume": [gd["nx"], gd["ny"], gd["nz"]], "voxel_mm": gd["vx"],
                    "detector": [gd["nu"], gd["nv"]], "pixel_mm": gd["du"], "angles": len(gd["angles"]),
-                   "dso_mm": gd["dso"], "dsd_mm": gd["dsd"], "solver": "cgls", "phantom": "40 seeded ellipsoids",
-                   "noise": "Poisson I0=1e5", "poisson_clamped_fraction": round(noise_info["clamped_fraction"], 5)},
+                   "dso_mm": gd["dso"], "dsd_mm": gd["dsd"], "solver": "cgls",
+                   "phantom": synth.WORKLOADS[wl]["phantom"]["kind"], "noise": synth.WORKLOADS[wl]["noise"],
+                   "poisson_clamped_fraction": round(noise_info.get("clamped_fraction", 0.0), 5)},
         "fwd_grays_per_s": round(n_rays / (fwd_ms / 1000.0) / 1e9, 3),
-        "fwd_hit_grays_per_s": round(stats["hit_rays"] / (fwd_ms / 1000.0) / 1e9, 3),
+        "fwd_hit_grays_per_s": (round(stats["hit_rays"] / (fwd_ms / 1000.0) / 1e9, 3)
+                                if stats["hit_rays"] else None),
         "bwd_gvoxel_views_per_s": round(n_vv / (bwd_ms / 1000.0) / 1e9, 3),
         "fwd_ms": round(fwd_ms, 3), "bwd_ms": round(bwd_ms, 3),
-        "segments_per_s": round(nnz / (fwd_ms / 1000.0) / 1e9, 2),
+        "gsegments_per_s": round(nnz / (fwd_ms / 1000.0) / 1e9, 2) if nnz else None,
         "lsqr_it_per_s": round(lsqr_rate, 3), "lsmr_it_per_s": round(lsmr_rate, 3),
-        "solves": solves, "roofline": roofline, "cpu_baseline": cpu,
+        "solves": solves, "serving": serving, "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 

@@ -119,6 +119,20 @@ kct_status kct_forward(kct_plan *plan, const void *d_vol, int32_t vol_dtype, voi
 kct_status kct_backproject(kct_plan *plan, const void *d_proj, int32_t proj_dtype, void *d_vol,
                            int32_t vol_dtype, void *stream);
 
+/*
+ * Unmatched back projection d_vol = B d_proj (paper Sec. 2.1.4: GPU
+ * toolboxes back-project with an approximation B of A^T; AB- and BA-GMRES
+ * take such a B as preconditioner).  Voxel-driven: the centre of each voxel
+ * is projected onto the detector, the projection of every angle is
+ * interpolated bilinearly there (zero outside the detector) and weighted by
+ * V / (du dv) * (DSD / w)^2 * |d| / DSD, with w the voxel's depth along the
+ * central ray and |d| the source-to-pixel distance at its image, so that B
+ * equals A^T on smooth data.  Layouts and storage pairs as kct_backproject;
+ * FP32 sums in angle order.  Enqueued on `stream`.
+ */
+kct_status kct_backproject_interp(kct_plan *plan, const void *d_proj, int32_t proj_dtype, void *d_vol,
+                                  int32_t vol_dtype, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Solvers                                                                   */
 /* ------------------------------------------------------------------------ */
@@ -127,17 +141,50 @@ typedef enum kct_solver {
     KCT_CGLS = 0,        /* Sec. 2.1.1; damped by lambda (Sec. 2.2, augmented system) */
     KCT_LSQR = 1,        /* Sec. 2.1.2; damped by lambda                              */
     KCT_LSMR = 2,        /* Sec. 2.1.3; damped by lambda                              */
-    KCT_HYBRID_LSQR = 3, /* Sec. 2.2.1 with a fixed lambda; stores the basis V_k      */
-    KCT_IRN_TV_CGLS = 4  /* Sec. 2.3.1: IRN majorants of isotropic TV, inner CGLS     */
+    KCT_HYBRID_LSQR = 3, /* Sec. 2.2.1; stores the basis V_k; lambda fixed or chosen
+                            at every iteration (kct_lambda_rule)                    */
+    KCT_IRN_TV_CGLS = 4, /* Sec. 2.3.1: IRN majorants of isotropic TV, inner CGLS     */
+    KCT_AB_GMRES = 5,    /* Sec. 2.1.4: GMRES on A B (B = the chosen back projector
+                            as right preconditioner); stores k+1 projection-space
+                            basis vectors                                          */
+    KCT_BA_GMRES = 6     /* Sec. 2.1.4: GMRES on B A (left preconditioner); stores
+                            k+1 volume-space basis vectors                         */
 } kct_solver;
+
+/* The back projector B of AB-/BA-GMRES.  Every other solver uses A^T. */
+typedef enum kct_backprojector {
+    KCT_BP_MATCHED = 0, /* the exact transpose A^T (kct_backproject)             */
+    KCT_BP_INTERP = 1   /* the interpolating B of kct_backproject_interp          */
+} kct_backprojector;
+
+/* How hybrid LSQR sets the Tikhonov parameter lambda_k of its projected
+ * problem (Sec. 2.2.2).  Every other solver takes KCT_LAMBDA_FIXED.
+ *   FIXED: lambda_k = params.lambda.
+ *   GCV:   lambda_k minimises the GCV function of the projected problem
+ *          (B_k, ||b|| e_1), searched on a log grid sigma_max * 10^[-7, 1]
+ *          (81 points) and refined by 60 golden-section steps.
+ *   DP:    lambda_k makes the projected residual equal noise_level * ||b||
+ *          (discrepancy principle); 0 while even lambda = 0 leaves a larger
+ *          residual, +inf (x = 0) when noise_level >= 1.
+ * Both use the SVD of B_k (one-sided Jacobi in FP64 on the device). */
+typedef enum kct_lambda_rule {
+    KCT_LAMBDA_FIXED = 0,
+    KCT_LAMBDA_GCV = 1,
+    KCT_LAMBDA_DP = 2
+} kct_lambda_rule;
 
 /* Columns of one history row (FP64), one row per iteration (for IRN-TV: per
  * inner iteration).
  *   [0] residual norm the method recurs: CGLS ||b - A x_k||, LSQR and hybrid
- *       ||[b;0] - [A; lam I] x_k||, LSMR ||[A; lam I]^T r_k||, IRN-TV ||b - A x||;
- *   [1] alpha_k; [2] beta_k (the method's own two leading scalars);
- *   [3] 1 if the method had broken down (zero norm) by this iteration, else 0. */
-#define KCT_HIST_COLS 4
+ *       ||[b;0] - [A; lam I] x_k||, LSMR ||[A; lam I]^T r_k||, IRN-TV ||b - A x||,
+ *       AB-GMRES ||b - A x_k||, BA-GMRES ||B (b - A x_k)||;
+ *   [1] alpha_k; [2] beta_k (the method's own two leading scalars; GMRES:
+ *       H[k+1, k] and the k-th diagonal entry of the rotated Hessenberg matrix);
+ *   [3] 1 if the method had broken down (zero norm) by this iteration, 2 if a
+ *       scalar became non-finite, else 0;
+ *   [4] lambda_k, the Tikhonov parameter of iteration k (the fixed lambda, or
+ *       hybrid LSQR's GCV / DP choice; IRN-TV: the TV weight lambda). */
+#define KCT_HIST_COLS 5
 
 typedef struct kct_solve_params {
     int32_t solver;    /* kct_solver                                            */
@@ -148,7 +195,10 @@ typedef struct kct_solve_params {
     double tv_eps;     /* IRN-TV smoothing epsilon of the weights                */
     int32_t vec_dtype; /* storage of the vectors the projectors read and write:
                           KCT_F32, KCT_BF16 or KCT_F16; x is always FP32       */
-    int32_t reserved;
+    int32_t lambda_rule; /* kct_lambda_rule; not FIXED only for hybrid LSQR      */
+    double noise_level;  /* DP: relative noise level ||e|| / ||b||, in (0, inf)  */
+    int32_t backprojector; /* kct_backprojector; not MATCHED only for the GMRES  */
+    int32_t reserved;    /* 0                                                    */
 } kct_solve_params;
 
 /* Workspace bytes kct_solve needs for `params` on `plan`. */

@@ -12,8 +12,12 @@ Contents
                 A^T y (C, OpenMP; ``siddon.c``), paper Sec. 1 eq. (original_pbm).
   dense.py      brute-force dense A for tiny grids, closed-form box and
                 sphere chords (NumPy).
-  solvers.py    CGLS, LSQR, LSMR (all with Tikhonov damping), hybrid LSQR with
-                fixed lambda, isotropic TV and IRN-TV with inner CGLS (NumPy).
+  interp.py     the unmatched, voxel-driven interpolating back projector B that
+                GPU toolboxes use in place of A^T (NumPy), Sec. 2.1.4.
+  solvers.py    CGLS, LSQR, LSMR (all with Tikhonov damping), hybrid LSQR
+                with lambda fixed or chosen by GCV / the discrepancy principle,
+                AB- and BA-GMRES, isotropic TV and IRN-TV with inner CGLS
+                (NumPy).
 
 Pins (``tests/test_oracle_*.py``, all CPU-only) tie each function to
 something other than itself: closed-form chords, brute force on tiny grids,
@@ -23,7 +27,7 @@ independent LSQR/LSMR, dense normal-equation solves, and hand-derived values
 in ``tests/golden/``.  No function here is "parity unpinned".
 """
 from .projector import Geometry, adjoint, build, count_nnz, forward, forward_rays, num_threads, ray_segments
-from . import dense, solvers
+from . import dense, interp, solvers
 
 __all__ = ["Geometry", "forward", "adjoint", "forward_rays", "ray_segments", "count_nnz", "num_threads", "build",
-           "dense", "solvers"]
+           "dense", "interp", "solvers"]

@@ -18,8 +18,11 @@ works it cites for each method).  Equations are named by their labels:
   * LSMR      -- Sec. 2.1.3, eq. (proj_LSMR): minimises ||A^T r_k|| over the
                  same Krylov space (Fong and Saunders 2011), damped form.
   * hybrid    -- Sec. 2.2.1, eq. (hybrid_LSQR): Tikhonov on the projected
-                 problem with a fixed lambda, solved densely on the stored
-                 bidiagonal matrix.
+                 problem, solved through the SVD of the stored bidiagonal
+                 matrix, with lambda fixed or chosen at every iteration by
+                 GCV or the discrepancy principle (Sec. 2.2.2).
+  * AB-/BA-GMRES -- Sec. 2.1.4: GMRES on A B (B a right preconditioner) or
+                 on B A (left), for a back projector B that need not be A^T.
   * IRN-TV    -- Sec. 2.3, eqs. (TV), (TV_reweighted), (TV_approx) and
                  Sec. 2.3.1: reweighted quadratic majorants of isotropic TV, each
                  solved by CGLS on [A; lam L D].
@@ -214,29 +217,207 @@ def golub_kahan(A, AT, b, k):
     return Us, Vs, B, beta1
 
 
-def hybrid_lsqr(A, AT, b, n_iter, lam):
-    """x_k = V_k y_k, y_k = argmin ||beta1 e1 - B_k y||^2 + lam^2 ||y||^2.
+def _projected_svd(Bk, beta1):
+    """SVD of the projected matrix: singular values s (k, descending), right
+    singular vectors Q (k x k, columns), and c = P^T (beta1 e1) (k+1 entries;
+    c[k] is the part of beta1 e1 outside the range of B_k)."""
+    P, s, Qt = np.linalg.svd(Bk, full_matrices=True)
+    return s, Qt.T, beta1 * P[0, :]
 
-    The projected problem is solved at every k by dense FP64 least squares on
-    [B_k; lam I].  hist: 'res' = ||[beta1 e1; 0] - [B_k; lam I] y_k|| (the
-    residual of the projected Tikhonov problem, equal to the augmented-system
-    residual because U_{k+1} has orthonormal columns), 'y' = the last y_k.
+
+def _filters(s, lam):
+    """Tikhonov filter factors s^2 / (s^2 + lam^2); 0 where s = 0."""
+    s2 = s * s
+    with np.errstate(invalid="ignore", divide="ignore"):
+        f = np.where(s2 > 0, s2 / (s2 + lam * lam), 0.0)
+    return f
+
+
+def projected_residual2(s, c, lam):
+    """||(I - B_k B_k^dagger(lam)) beta1 e1||^2, the squared data residual of
+    the projected Tikhonov solution (equal to ||A x_k - b||^2 while U_{k+1} has
+    orthonormal columns)."""
+    k = s.size
+    f = _filters(s, lam)
+    return float(np.sum(((1.0 - f) * c[:k]) ** 2) + c[k] ** 2)
+
+
+def gcv(s, c, lam):
+    """GCV function of the projected problem (Sec. 2.2.2, GCV equation), with
+    B^dagger(lam) = (B^T B + lam^2 I)^-1 B^T: the squared residual over the
+    squared trace of I_{k+1} - B B^dagger(lam) = 1 + sum_i (1 - f_i)."""
+    f = _filters(s, lam)
+    return projected_residual2(s, c, lam) / (1.0 + float(np.sum(1.0 - f))) ** 2
+
+
+GCV_GRID = 81          # log10 lambda grid: sigma_max * 10^[-7, 1], 0.1 decade apart
+GCV_GOLDEN_STEPS = 60  # golden-section steps on the bracketing grid cells
+DP_BISECT_STEPS = 64   # bisection steps on log10 lambda in sigma_max * 10^[-12, 8]
+
+
+def lambda_gcv(s, c):
+    """Minimiser of the projected GCV function: the smallest value on a
+    log-spaced grid, refined by golden-section search over its two grid
+    cells (the paper states the minimisation, not how it is carried out)."""
+    if s.size == 0 or s[0] == 0.0:
+        return 0.0
+    L = np.log10(s[0])
+    grid = L - 7.0 + 8.0 * np.arange(GCV_GRID) / (GCV_GRID - 1)
+    G = [gcv(s, c, 10.0 ** g) for g in grid]
+    j = int(np.argmin(G))
+    a, b = grid[max(j - 1, 0)], grid[min(j + 1, GCV_GRID - 1)]
+    r = (np.sqrt(5.0) - 1.0) / 2.0
+    x1, x2 = b - r * (b - a), a + r * (b - a)
+    f1, f2 = gcv(s, c, 10.0 ** x1), gcv(s, c, 10.0 ** x2)
+    for _ in range(GCV_GOLDEN_STEPS):
+        if f1 <= f2:
+            b, x2, f2 = x2, x1, f1
+            x1 = b - r * (b - a)
+            f1 = gcv(s, c, 10.0 ** x1)
+        else:
+            a, x1, f1 = x1, x2, f2
+            x2 = a + r * (b - a)
+            f2 = gcv(s, c, 10.0 ** x2)
+    return float(10.0 ** (0.5 * (a + b)))
+
+
+def lambda_dp(s, c, target):
+    """Discrepancy principle (Sec. 2.2.2, DP equations): the lambda at which
+    the projected squared residual equals target = (nl ||b||)^2.  The
+    residual grows with lambda from c_k^2 (lambda = 0) to beta1^2, so: 0 when
+    even lambda = 0 leaves a residual at or above the target, +inf when the
+    target is at or above ||b||^2, else the root by bisection on log10
+    lambda."""
+    k = s.size
+    if k == 0 or s[0] == 0.0:
+        return 0.0
+    if c[k] ** 2 >= target:
+        return 0.0
+    if float(np.sum(c * c)) <= target:
+        return float("inf")
+    L = np.log10(s[0])
+    lo, hi = L - 12.0, L + 8.0
+    for _ in range(DP_BISECT_STEPS):
+        mid = 0.5 * (lo + hi)
+        if projected_residual2(s, c, 10.0 ** mid) < target:
+            lo = mid
+        else:
+            hi = mid
+    return float(10.0 ** (0.5 * (lo + hi)))
+
+
+def hybrid_lsqr(A, AT, b, n_iter, lam, rule="fixed", noise_level=None):
+    """x_k = V_k y_k, y_k = argmin ||beta1 e1 - B_k y||^2 + lam_k^2 ||y||^2
+    (Sec. 2.2.1, eq. (hybrid_LSQR)).
+
+    lam_k is ``lam`` (rule "fixed"), the GCV minimiser (rule "gcv"), or the
+    discrepancy-principle root for the relative noise level
+    ``noise_level`` = ||e|| / ||b|| (rule "dp"), recomputed at every k from
+    the SVD of B_k.  y_k = Q diag(s / (s^2 + lam_k^2)) c[:k].  hist: 'res' =
+    ||[beta1 e1; 0] - [B_k; lam_k I] y_k|| (the projected Tikhonov residual,
+    equal to the augmented-system residual while U_{k+1} is orthonormal),
+    'lam' = lam_k, 'y' = the last y_k.
     """
+    if rule not in ("fixed", "gcv", "dp"):
+        raise ValueError(rule)
     Us, Vs, B, beta1 = golub_kahan(A, AT, b, n_iter)
-    hist = {"res": []}
+    hist = {"res": [], "lam": []}
     y = np.zeros(0)
     for k in range(1, B.shape[1] + 1):
-        Bk = B[: k + 1, :k]
-        M = np.vstack([Bk, lam * np.eye(k)])
-        rhs = np.zeros(2 * k + 1)
-        rhs[0] = beta1
-        y, *_ = np.linalg.lstsq(M, rhs, rcond=None)
-        hist["res"].append(float(np.linalg.norm(M @ y - rhs)))
+        s, Q, c = _projected_svd(B[: k + 1, :k], beta1)
+        if rule == "gcv":
+            lk = lambda_gcv(s, c)
+        elif rule == "dp":
+            lk = lambda_dp(s, c, (noise_level * beta1) ** 2)
+        else:
+            lk = float(lam)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            g = np.where(s > 0, s / (s * s + lk * lk), 0.0) if np.isfinite(lk) else np.zeros_like(s)
+        y = Q @ (g * c[:k])
+        pen = 0.0 if not np.isfinite(lk) else lk * lk * float(np.dot(y, y))
+        hist["res"].append(float(np.sqrt(projected_residual2(s, c, lk) + pen)) if np.isfinite(lk)
+                           else float(beta1))
+        hist["lam"].append(lk)
     x = np.zeros_like(Vs[0]) if Vs else np.zeros_like(AT(np.asarray(b, dtype=np.float64)))
     for i, yi in enumerate(y):
         x = x + yi * Vs[i]
     hist["y"] = y
     hist["res"] = np.asarray(hist["res"])
+    hist["lam"] = np.asarray(hist["lam"])
+    return x, hist
+
+
+# --------------------------------------------------------------------------
+# AB- and BA-GMRES with a back projector B (Sec. 2.1.4).
+# --------------------------------------------------------------------------
+def _arnoldi(op, r0, k):
+    """k steps of Arnoldi (modified Gram-Schmidt) on ``op`` from r0.
+
+    Returns (V, H, beta) with V the basis vectors (up to k+1), H the
+    (j+1) x j upper Hessenberg matrix of the steps taken, beta = ||r0||;
+    stops early when a new vector has zero norm.
+    """
+    r0 = np.asarray(r0, dtype=np.float64)
+    v, beta = _normalise(r0.copy())
+    V = [v]
+    H = np.zeros((k + 1, k))
+    j = 0
+    for j in range(k):
+        if beta == 0.0:
+            return V[:1], H[:1, :0], beta
+        w = np.asarray(op(V[j]), dtype=np.float64).copy()
+        for i in range(j + 1):
+            H[i, j] = _dot(w, V[i])
+            w = w - H[i, j] * V[i]
+        h = _nrm(w)
+        H[j + 1, j] = h
+        if h == 0.0:
+            return V, H[: j + 2, : j + 1], beta
+        V.append(w / h)
+    return V, H[: k + 1, :k], beta
+
+
+def _gmres_coeffs(H, beta):
+    """y = argmin ||beta e1 - H y|| (dense FP64 least squares); and the residual."""
+    rhs = np.zeros(H.shape[0])
+    rhs[0] = beta
+    if H.shape[1] == 0:
+        return np.zeros(0), beta
+    y, *_ = np.linalg.lstsq(H, rhs, rcond=None)
+    return y, float(np.linalg.norm(rhs - H @ y))
+
+
+def _gmres_run(op, r0, n_iter):
+    """Arnoldi once for n_iter steps; the GMRES iterate of step k uses only
+    the leading (k+1) x k block of H.  Returns (V, y of the last step, hist)."""
+    V, H, beta = _arnoldi(op, r0, n_iter)
+    hist = {"res": []}
+    y = np.zeros(0)
+    for k in range(1, n_iter + 1):
+        kk = min(k, H.shape[1])
+        y, res = _gmres_coeffs(H[: kk + 1, :kk], beta)
+        hist["res"].append(res)
+    hist["res"] = np.asarray(hist["res"])
+    return V, y, hist
+
+
+def ab_gmres(A, B, b, n_iter):
+    """AB-GMRES: x_k = B y_k with y_k = argmin ||b - A B y|| over K_k(AB, b)
+    (GMRES on AB, B a right preconditioner).  hist 'res' = ||b - A x_k||
+    (the GMRES residual of iteration k).  With B = A^T this is LSQR."""
+    b = np.asarray(b, dtype=np.float64)
+    V, y, hist = _gmres_run(lambda z: A(B(z)), b, n_iter)
+    z = sum(yi * V[i] for i, yi in enumerate(y)) if len(y) else np.zeros_like(b)
+    return B(z), hist
+
+
+def ba_gmres(A, B, b, n_iter):
+    """BA-GMRES: x_k = argmin ||B (b - A x)|| over K_k(BA, B b) (GMRES on BA,
+    B a left preconditioner).  hist 'res' = ||B (b - A x_k)||.  With B = A^T
+    this is LSMR."""
+    r0 = B(np.asarray(b, dtype=np.float64))
+    V, y, hist = _gmres_run(lambda z: B(A(z)), r0, n_iter)
+    x = sum(yi * V[i] for i, yi in enumerate(y)) if len(y) else np.zeros_like(r0)
     return x, hist
 
 

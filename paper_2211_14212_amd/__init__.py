@@ -24,7 +24,7 @@ from ._lib import (KCT_BF16, KCT_CGLS, KCT_F16, KCT_F32, KCT_HIST_COLS, KCT_HYBR
 __all__ = ["Geometry", "Plan", "State", "SOLVERS", "require_gpu", "KctError", "dtype_code", "library_path"]
 
 SOLVERS = {"cgls": KCT_CGLS, "lsqr": KCT_LSQR, "lsmr": KCT_LSMR, "hybrid_lsqr": KCT_HYBRID_LSQR,
-           "irn_tv_cgls": KCT_IRN_TV_CGLS}
+           "irn_tv_cgls": KCT_IRN_TV_CGLS, "ab_gmres": _lib.KCT_AB_GMRES, "ba_gmres": _lib.KCT_BA_GMRES}
 _DT = {torch.float32: KCT_F32, torch.bfloat16: KCT_BF16, torch.float16: KCT_F16}
 
 
@@ -95,10 +95,19 @@ def _stream_ptr(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def _params(solver, n_iter, lam, vec_dtype, tv_outer=0, tv_inner=0, tv_eps=1e-3):
+LAMBDA_RULES = {"fixed": _lib.KCT_LAMBDA_FIXED, "gcv": _lib.KCT_LAMBDA_GCV, "dp": _lib.KCT_LAMBDA_DP}
+
+
+BACKPROJECTORS = {"matched": _lib.KCT_BP_MATCHED, "interp": _lib.KCT_BP_INTERP}
+
+
+def _params(solver, n_iter, lam, vec_dtype, tv_outer=0, tv_inner=0, tv_eps=1e-3, lam_rule="fixed",
+            noise_level=0.0, backprojector="matched"):
     code = SOLVERS[solver] if isinstance(solver, str) else int(solver)
+    rule = LAMBDA_RULES[lam_rule] if isinstance(lam_rule, str) else int(lam_rule)
+    bp = BACKPROJECTORS[backprojector] if isinstance(backprojector, str) else int(backprojector)
     return _lib.KctSolveParams(code, int(n_iter), float(lam), int(tv_outer), int(tv_inner), float(tv_eps),
-                               dtype_code(vec_dtype), 0)
+                               dtype_code(vec_dtype), rule, float(noise_level), bp, 0)
 
 
 class Plan:
@@ -169,6 +178,19 @@ class Plan:
                                                    _stream_ptr(stream)), "kct_backproject")
         return out
 
+    def backproject_interp(self, proj: torch.Tensor, out: torch.Tensor | None = None, out_dtype=None, stream=None):
+        """B proj: the unmatched, voxel-driven interpolating back projection, (nz, ny, nx)."""
+        self._check(proj, self.geom.proj_shape, "projections")
+        if out is None:
+            out = torch.empty(self.geom.vol_shape, dtype=out_dtype or proj.dtype, device=self.device)
+        self._check(out, self.geom.vol_shape, "volume")
+        with torch.cuda.device(self.device):
+            _lib.check(_lib.load().kct_backproject_interp(self._h, ctypes.c_void_p(proj.data_ptr()),
+                                                          dtype_code(proj.dtype), ctypes.c_void_p(out.data_ptr()),
+                                                          dtype_code(out.dtype), _stream_ptr(stream)),
+                       "kct_backproject_interp")
+        return out
+
     # -- solvers ----------------------------------------------------------
     def workspace_bytes(self, solver="cgls", n_iter=20, lam=0.0, vec_dtype=torch.float32, **tv) -> int:
         p = _params(solver, n_iter, lam, vec_dtype, **tv)
@@ -186,8 +208,11 @@ class Plan:
               stream=None, **tv):
         """Run `solver` from x0 = 0 for `n_iter` iterations.  Returns (x, history).
 
-        history is an (n_rows, 4) float64 device tensor (see KCT_HIST_COLS) or None.
-        The call only enqueues work on the stream.
+        Keyword options: tv_outer, tv_inner, tv_eps (IRN-TV); lam_rule
+        ("fixed", "gcv" or "dp") and noise_level (hybrid LSQR); backprojector
+        ("matched" or "interp", AB-/BA-GMRES).  history is an
+        (n_rows, KCT_HIST_COLS) float64 device tensor or None.  The call only
+        enqueues work on the stream.
         """
         self._check(b, self.geom.proj_shape, "b")
         if b.dtype != torch.float32:

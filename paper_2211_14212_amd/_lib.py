@@ -19,11 +19,16 @@ STATUS_NAMES = {0: "KCT_OK", 1: "KCT_E_INVALID_ARG", 2: "KCT_E_GEOMETRY", 3: "KC
 # kct_dtype
 KCT_F32, KCT_BF16, KCT_F16 = 0, 1, 2
 # kct_solver
-KCT_CGLS, KCT_LSQR, KCT_LSMR, KCT_HYBRID_LSQR, KCT_IRN_TV_CGLS = 0, 1, 2, 3, 4
-KCT_HIST_COLS = 4
+KCT_CGLS, KCT_LSQR, KCT_LSMR, KCT_HYBRID_LSQR, KCT_IRN_TV_CGLS, KCT_AB_GMRES, KCT_BA_GMRES = 0, 1, 2, 3, 4, 5, 6
+# kct_backprojector
+KCT_BP_MATCHED, KCT_BP_INTERP = 0, 1
+KCT_HIST_COLS = 5
+# kct_lambda_rule
+KCT_LAMBDA_FIXED, KCT_LAMBDA_GCV, KCT_LAMBDA_DP = 0, 1, 2
 
 EXPORTED = [
     "kct_plan_create", "kct_plan_destroy", "kct_plan_device_bytes", "kct_forward", "kct_backproject",
+    "kct_backproject_interp",
     "kct_solve_workspace_bytes", "kct_solve", "kct_state_create", "kct_state_step", "kct_state_progress",
     "kct_state_destroy", "kct_status_str", "kct_last_error", "kct_version",
 ]
@@ -46,7 +51,8 @@ class KctSolveParams(ctypes.Structure):
     _fields_ = [
         ("solver", ctypes.c_int32), ("n_iter", ctypes.c_int32), ("lam", ctypes.c_double),
         ("tv_outer", ctypes.c_int32), ("tv_inner", ctypes.c_int32), ("tv_eps", ctypes.c_double),
-        ("vec_dtype", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("vec_dtype", ctypes.c_int32), ("lambda_rule", ctypes.c_int32), ("noise_level", ctypes.c_double),
+        ("backprojector", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 
@@ -77,6 +83,7 @@ def load(path: str = LIB_PATH):
         "kct_plan_device_bytes": ([vp, P(sz)], st),
         "kct_forward": ([vp, vp, i32, vp, i32, vp], st),
         "kct_backproject": ([vp, vp, i32, vp, i32, vp], st),
+        "kct_backproject_interp": ([vp, vp, i32, vp, i32, vp], st),
         "kct_solve_workspace_bytes": ([vp, P(KctSolveParams), P(sz)], st),
         "kct_solve": ([vp, P(KctSolveParams), vp, vp, vp, sz, vp, vp], st),
         "kct_state_create": ([vp, P(KctSolveParams), vp, vp, vp, sz, vp, vp, P(vp)], st),
@@ -88,6 +95,8 @@ def load(path: str = LIB_PATH):
         "kct_version": ([], ctypes.c_char_p),
         "kct_debug_take_error_flag": ([vp], ctypes.c_int),
         "kct_debug_bwd_shape": ([vp, P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_int)], None),
+        "kct_debug_bwd_shape_geom": ([P(KctGeometry), P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_int),
+                                      P(ctypes.c_int)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

@@ -1,8 +1,10 @@
 // Plan creation, geometry validation, errors and the plain projector calls.
 
+#include "gmres.hpp"
 #include "kct_internal.hpp"
 
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -160,15 +162,22 @@ kct_status kct_plan_create(const kct_geometry *geom, int device, kct_plan **out)
         delete p;
         return s;
     }
+    // Tuning override: KCT_FWD_PREFETCH=0 selects the forward loop without
+    // the one-step-ahead gather.
+    if (const char *e = std::getenv("KCT_FWD_PREFETCH")) p->fwd_prefetch = std::atoi(e) != 0;
     DeviceGuard dg(device);
     if (!dg.ok) {
         delete p;
         return fail(KCT_E_DEVICE, "hipSetDevice failed");
     }
+    // 1/v per detector row.  The central row of an odd detector (v = 0) gets
+    // 1e300 instead of infinity: z/v then maps a voxel with z0 <= 0 < z1 to an
+    // interval covering every ray parameter in (0, 1) and excludes the others,
+    // which is the half-open voxel rule for a ray inside the plane z = 0.
     std::vector<double> invv(geom->nv);
     for (int iv = 0; iv < geom->nv; ++iv) {
         const double v = (iv - p->gp.cv) * geom->dv;
-        invv[iv] = v != 0.0 ? 1.0 / v : 0.0;
+        invv[iv] = v != 0.0 ? 1.0 / v : 1.0e300;
     }
     s = check_hip(hipMalloc(&p->d_tab, sizeof(AngleGeo) * geom->n_angles), "plan table allocation");
     if (s == KCT_OK) s = check_hip(hipMalloc(&p->d_invv, sizeof(double) * geom->nv), "plan table allocation");
@@ -241,6 +250,17 @@ kct_status kct_backproject(kct_plan *p, const void *d_proj, int32_t proj_dtype, 
     return launch_backward(*p, d_proj, proj_dtype, d_vol, vol_dtype, ep, static_cast<hipStream_t>(stream));
 }
 
+kct_status kct_backproject_interp(kct_plan *p, const void *d_proj, int32_t proj_dtype, void *d_vol, int32_t vol_dtype,
+                                  void *stream)
+{
+    g_last_error.clear();
+    if (!p || !d_vol || !d_proj) return fail(KCT_E_INVALID_ARG, "NULL argument");
+    if (!dtype_ok(vol_dtype) || !dtype_ok(proj_dtype)) return fail(KCT_E_DTYPE, "unknown storage type");
+    DeviceGuard dg(p->device);
+    Epilogue ep;
+    return launch_interp_backward(*p, d_proj, proj_dtype, d_vol, vol_dtype, ep, static_cast<hipStream_t>(stream));
+}
+
 // Test hook (not in kct.h): read and clear the back projector's footprint
 // overflow flag.  Synchronises the device.
 int kct_debug_take_error_flag(kct_plan *p)
@@ -252,6 +272,26 @@ int kct_debug_take_error_flag(kct_plan *p)
     if (hipMemcpy(&v, p->d_err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return -1;
     (void)hipMemset(p->d_err, 0, sizeof(int));
     return v;
+}
+
+// Test hook: the back projector launch shape a plan for `geom` would use,
+// computed on the host without touching a device.  Returns a kct_status.
+int kct_debug_bwd_shape_geom(const kct_geometry *geom, int *kz, int *ncmax, int *pw, int *ph)
+{
+    kct_status s = validate(geom);
+    if (s != KCT_OK) return s;
+    Plan p;
+    p.geom = *geom;
+    p.angles.assign(geom->angles, geom->angles + geom->n_angles);
+    p.geom.angles = p.angles.data();
+    build_tables(p);
+    s = choose_bwd_shape(p);
+    if (s != KCT_OK) return s;
+    if (kz) *kz = p.bwd_kz;
+    if (ncmax) *ncmax = p.bwd_ncmax;
+    if (pw) *pw = p.bwd_pw;
+    if (ph) *ph = p.bwd_ph;
+    return KCT_OK;
 }
 
 // Test hook: the back projector launch shape chosen for the plan.

@@ -81,6 +81,7 @@ enum ScalarIdx : int {
     S_ALPHABAR, S_ZETABAR, S_RHO_OLD, S_RHOBAR_OLD, S_CBAR, S_SBAR,
     S_LAMBDA, S_PNORM2, S_LAST,
     S_DONE, S_ITER, S_HROW, S_KGK, S_RES,
+    S_HLAM,                        // lambda reported in history column 4
     // Coefficients the scalar kernels leave for the next vector kernels:
     S_F0 = 24, S_F1,               // forward projector epilogue (2)
     S_B0, S_B1, S_B2, S_B3,        // back projector epilogue (4)
@@ -102,7 +103,9 @@ struct Plan {
     size_t pad_bytes = 0;        // capacity of d_pad
     int *d_err = nullptr;         // back projector footprint overflow flag (0 = fine)
     // Back projector launch shape (chosen from the geometry at plan creation).
-    int bwd_kz = 8, bwd_ncmax = 5, bwd_pw = 0, bwd_ph = 0;
+    int bwd_kz = 8, bwd_ncmax = 5, bwd_pw = 0, bwd_ph = 0, bwd_fp_angles = 0;
+    bool fwd_prefetch = true;     // forward projector gathers one segment ahead
+    bool bwd_acc_lds = true;      // back projector keeps per-voxel sums in LDS
     size_t bwd_lds = 0;
     int64_t n_vox() const { return int64_t(gp.nx) * gp.ny * gp.nz; }
     int64_t n_ray() const { return int64_t(gp.na) * gp.nv * gp.nu; }

@@ -41,6 +41,8 @@ kct_status sk_gk_beta(double *S, Reduced u, hipStream_t st);
 kct_status sk_lsqr_alpha(double *S, Reduced v, double *hist, double *gk, hipStream_t st);
 kct_status sk_lsmr_alpha(double *S, Reduced v, double *hist, hipStream_t st);
 kct_status sk_hybrid_solve(double *S, const double *gk, double *work, double *coef, hipStream_t st);
+kct_status sk_hybrid_choose(double *S, const double *gk, double *work, double *coef, double *hist, int rule,
+                            double noise_level, hipStream_t st);
 
 // Total variation (IRN-TV).
 int tv_num_groups(int64_t M);
@@ -51,7 +53,7 @@ kct_status tv_grad_store(const Plan &p, const void *v, int dt, const float *Lw, 
                          double c, bool accumulate, hipStream_t st);
 kct_status tv_adjoint_add(const Plan &p, void *s, int dt, const float *r2, const float *Lw, double lam,
                           const double *S, double *parts, hipStream_t st);
-kct_status sk_tv_restart(double *S, Reduced s, bool first, int n_rows, hipStream_t st);
+kct_status sk_tv_restart(double *S, Reduced s, bool first, int n_rows, double lam, hipStream_t st);
 kct_status sk_tv_alpha(double *S, Reduced q, Reduced t, double lam, hipStream_t st);
 
 } // namespace kct

@@ -173,6 +173,7 @@ __device__ inline void write_hist(double *hist, double *S, double res, double a,
             h[1] = a;
             h[2] = b;
             h[3] = S[S_DONE];
+            h[4] = S[S_HLAM];
         }
     }
     S[S_HROW] += 1.0;
@@ -187,6 +188,7 @@ __global__ __launch_bounds__(256) void k_sc_cgls_init(double *S, const double *p
     const double g = reduce_parts(pa, na);
     if (threadIdx.x != 0) return;
     S[S_LAMBDA] = lam;
+    S[S_HLAM] = lam;
     S[S_GAMMA] = g;
     S[S_PNORM2] = g;
     S[S_ITER] = n_iter;
@@ -249,6 +251,7 @@ __global__ __launch_bounds__(256) void k_sc_gk_init1(double *S, const double *pu
     if (threadIdx.x != 0) return;
     const double beta = sqrt(b2);
     S[S_LAMBDA] = lam;
+    S[S_HLAM] = lam;
     S[S_ITER] = n_iter;
     S[S_HROW] = 0.0;
     S[S_KGK] = 0.0;
@@ -456,6 +459,268 @@ __global__ __launch_bounds__(64) void k_hybrid_solve(double *S, const double *gk
     for (int c = 0; c < k; ++c) coef[c] /= gk[2 * c + 1];
 }
 
+// ---------------------------------------------------------------------------
+// Hybrid LSQR with lambda_k chosen at every iteration (GCV or discrepancy
+// principle on the projected problem).  One workgroup:
+//   1. B_k ((k+1) x k lower bidiagonal from the stored alpha, beta) is
+//      copied to W, and Q = I;
+//   2. one-sided Jacobi: pairs of columns of W are rotated until they are
+//      orthogonal (round-robin pair order, k/2 pairs per round, one thread per
+//      pair), the same rotations accumulate in Q; then sigma_i = ||W_i||,
+//      P_i = W_i / sigma_i, B_k = P diag(sigma) Q^T;
+//   3. c_i = beta_1 P_i[0] for i < k, and c_k = beta_1 / ||n|| with n the null
+//      vector of B_k^T (n_0 = 1, n_{j+1} = -alpha_{j+1} n_j / beta_{j+2}): the
+//      part of beta_1 e_1 outside the range of B_k;
+//   4. lambda_k by the rule (the same search as the oracle's);
+//   5. y = Q diag(sigma / (sigma^2 + lambda^2)) c, coef_i = y_i / alpha_i, and
+//      history row k gets the projected Tikhonov residual and lambda_k.
+// ---------------------------------------------------------------------------
+namespace hyb {
+
+constexpr int GRID = 81;       // log10 lambda grid: sigma_max * 10^[-7, 1]
+constexpr int GOLDEN = 60;     // golden-section steps
+constexpr int BISECT = 64;     // bisection steps on log10 lambda, sigma_max * 10^[-12, 8]
+constexpr int SWEEPS = 60;     // Jacobi sweep limit
+constexpr double EPS = 2.220446049250313e-16;
+
+__device__ inline double res2(const double *sig, const double *c, int k, double lam)
+{
+    double r = c[k] * c[k];
+    for (int i = 0; i < k; ++i) {
+        const double s2 = sig[i] * sig[i];
+        const double f = s2 > 0.0 ? s2 / (s2 + lam * lam) : 0.0;
+        const double t = (1.0 - f) * c[i];
+        r += t * t;
+    }
+    return r;
+}
+
+__device__ inline double gcv(const double *sig, const double *c, int k, double lam)
+{
+    double tr = 1.0;
+    for (int i = 0; i < k; ++i) {
+        const double s2 = sig[i] * sig[i];
+        tr += 1.0 - (s2 > 0.0 ? s2 / (s2 + lam * lam) : 0.0);
+    }
+    return res2(sig, c, k, lam) / (tr * tr);
+}
+
+} // namespace hyb
+
+__global__ __launch_bounds__(256) void k_hybrid_choose(double *S, const double *gk, double *work, double *coef,
+                                                       double *hist, int rule, double noise_level)
+{
+    using namespace hyb;
+    __shared__ int rotated;
+    __shared__ double grid_g[GRID];
+    __shared__ double sh_lam, sh_smax;
+    const int tid = threadIdx.x;
+    if (S[S_DONE] == 2.0) return;
+    const int k = int(S[S_KGK]);
+    if (k <= 0) return;
+    const int m = k + 1;
+    double *W = work;         // m x k, column-major
+    double *Q = W + m * k;    // k x k, column-major
+    double *sig = Q + k * k;  // k
+    double *c = sig + k;      // k + 1
+    double *y = c + k + 1;    // k
+    const double beta1 = gk[0];
+
+    for (int e = tid; e < m * k; e += 256) W[e] = 0.0;
+    for (int e = tid; e < k * k; e += 256) Q[e] = (e % (k + 1) == 0) ? 1.0 : 0.0;
+    __syncthreads();
+    for (int j = tid; j < k; j += 256) {
+        W[j * m + j] = gk[2 * j + 1];     // alpha_{j+1}
+        W[j * m + j + 1] = gk[2 * j + 2]; // beta_{j+2}
+    }
+    __syncthreads();
+
+    // Round-robin order over n2 (even) slots; slot k is empty when k is odd.
+    const int n2 = k + (k & 1);
+    // Rotate while |w_p . w_q| > (k+1) eps ||w_p|| ||w_q||, the rounding level
+    // of the dot products.
+    const double tol = double(m) * EPS;
+    for (int sweep = 0; sweep < SWEEPS && n2 > 1; ++sweep) {
+        if (tid == 0) rotated = 0;
+        __syncthreads();
+        for (int r = 0; r < n2 - 1; ++r) {
+            for (int pi = tid; pi < n2 / 2; pi += 256) {
+                int p, q;
+                if (pi == 0) {
+                    p = r;
+                    q = n2 - 1;
+                } else {
+                    p = (r + pi) % (n2 - 1);
+                    q = (r - pi + (n2 - 1)) % (n2 - 1);
+                }
+                if (p > q) {
+                    const int t = p;
+                    p = q;
+                    q = t;
+                }
+                if (q >= k) continue;
+                double *wp = W + p * m, *wq = W + q * m;
+                double a = 0.0, b = 0.0, g = 0.0;
+                for (int i = 0; i < m; ++i) {
+                    a += wp[i] * wp[i];
+                    b += wq[i] * wq[i];
+                    g += wp[i] * wq[i];
+                }
+                if (g != 0.0 && fabs(g) > tol * sqrt(a) * sqrt(b)) {
+                    const double zeta = (b - a) / (2.0 * g);
+                    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
+                    const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+                    for (int i = 0; i < m; ++i) {
+                        const double u = wp[i], v = wq[i];
+                        wp[i] = cs * u - sn * v;
+                        wq[i] = sn * u + cs * v;
+                    }
+                    double *qp = Q + p * k, *qq = Q + q * k;
+                    for (int i = 0; i < k; ++i) {
+                        const double u = qp[i], v = qq[i];
+                        qp[i] = cs * u - sn * v;
+                        qq[i] = sn * u + cs * v;
+                    }
+                    rotated = 1;
+                }
+            }
+            __syncthreads();
+        }
+        const int any = rotated;
+        __syncthreads();
+        if (!any) break;
+    }
+
+    for (int j = tid; j < k; j += 256) {
+        double s2 = 0.0;
+        for (int i = 0; i < m; ++i) s2 += W[j * m + i] * W[j * m + i];
+        const double sg = sqrt(s2);
+        sig[j] = sg;
+        c[j] = sg > 0.0 ? beta1 * W[j * m] / sg : 0.0;
+    }
+    if (tid == 0) {
+        // c_k from the null vector of B_k^T, rescaled to stay in range.
+        double n0 = 1.0, cur = 1.0, ssq = 1.0;
+        bool zero = false;
+        for (int j = 0; j < k && !zero; ++j) {
+            const double al = gk[2 * j + 1], be = gk[2 * j + 2];
+            if (be == 0.0) {
+                zero = true;
+                break;
+            }
+            cur = -al * cur / be;
+            ssq += cur * cur;
+            if (fabs(cur) > 1e100) {
+                cur *= 1e-100;
+                ssq *= 1e-200;
+                n0 *= 1e-100;
+            }
+        }
+        c[k] = zero ? 0.0 : beta1 * n0 / sqrt(ssq);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double smax = 0.0;
+        for (int j = 0; j < k; ++j) smax = fmax(smax, sig[j]);
+        sh_smax = smax;
+    }
+    __syncthreads();
+    const double smax = sh_smax;
+
+    if (rule == KCT_LAMBDA_GCV) {
+        const double L = log10(smax);
+        if (smax > 0.0 && tid < GRID) grid_g[tid] = gcv(sig, c, k, pow(10.0, L - 7.0 + 8.0 * tid / (GRID - 1)));
+        __syncthreads();
+        if (tid == 0) {
+            double lam = 0.0;
+            if (smax > 0.0) {
+                int j = 0;
+                for (int t = 1; t < GRID; ++t)
+                    if (grid_g[t] < grid_g[j]) j = t;
+                const double gj0 = L - 7.0 + 8.0 * max(j - 1, 0) / (GRID - 1);
+                const double gj1 = L - 7.0 + 8.0 * min(j + 1, GRID - 1) / (GRID - 1);
+                double a = gj0, b = gj1;
+                const double rr = (sqrt(5.0) - 1.0) / 2.0;
+                double x1 = b - rr * (b - a), x2 = a + rr * (b - a);
+                double f1 = gcv(sig, c, k, pow(10.0, x1)), f2 = gcv(sig, c, k, pow(10.0, x2));
+                for (int it = 0; it < GOLDEN; ++it) {
+                    if (f1 <= f2) {
+                        b = x2;
+                        x2 = x1;
+                        f2 = f1;
+                        x1 = b - rr * (b - a);
+                        f1 = gcv(sig, c, k, pow(10.0, x1));
+                    } else {
+                        a = x1;
+                        x1 = x2;
+                        f1 = f2;
+                        x2 = a + rr * (b - a);
+                        f2 = gcv(sig, c, k, pow(10.0, x2));
+                    }
+                }
+                lam = pow(10.0, 0.5 * (a + b));
+            }
+            sh_lam = lam;
+        }
+    } else if (tid == 0) {
+        double lam = 0.0;
+        if (rule == KCT_LAMBDA_DP && smax > 0.0) {
+            const double target = (noise_level * beta1) * (noise_level * beta1);
+            double call = 0.0;
+            for (int j = 0; j <= k; ++j) call += c[j] * c[j];
+            if (c[k] * c[k] >= target) {
+                lam = 0.0;
+            } else if (call <= target) {
+                lam = HUGE_VAL;
+            } else {
+                const double L = log10(smax);
+                double lo = L - 12.0, hi = L + 8.0;
+                for (int it = 0; it < BISECT; ++it) {
+                    const double mid = 0.5 * (lo + hi);
+                    if (res2(sig, c, k, pow(10.0, mid)) < target) lo = mid;
+                    else hi = mid;
+                }
+                lam = pow(10.0, 0.5 * (lo + hi));
+            }
+        } else if (rule == KCT_LAMBDA_FIXED) {
+            lam = S[S_LAMBDA];
+        }
+        sh_lam = lam;
+    }
+    __syncthreads();
+    const double lam = sh_lam;
+    const bool inf = !(lam < HUGE_VAL);
+
+    for (int r = tid; r < k; r += 256) {
+        double v = 0.0;
+        if (!inf)
+            for (int i = 0; i < k; ++i) {
+                const double s2 = sig[i] * sig[i];
+                const double gi = s2 > 0.0 ? sig[i] / (s2 + lam * lam) : 0.0;
+                v += Q[i * k + r] * (gi * c[i]);
+            }
+        y[r] = v;
+        coef[r] = v / gk[2 * r + 1];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double res = beta1;
+        if (!inf) {
+            double yy = 0.0;
+            for (int r = 0; r < k; ++r) yy += y[r] * y[r];
+            res = sqrt(res2(sig, c, k, lam) + lam * lam * yy);
+        }
+        S[S_HLAM] = lam;
+        if (hist) {
+            const int64_t row = int64_t(S[S_HROW]) - 1;
+            if (row >= 0 && row < int64_t(S[S_ITER])) {
+                hist[row * KCT_HIST_COLS + 0] = res;
+                hist[row * KCT_HIST_COLS + 4] = lam;
+            }
+        }
+    }
+}
+
 int vec_groups(int64_t n)
 {
     const int64_t g = (n + 1023) / 1024;
@@ -597,6 +862,12 @@ kct_status sk_hybrid_solve(double *S, const double *gk, double *work, double *co
 {
     SC1(k_hybrid_solve, dim3(1), dim3(64), 0, st, S, gk, work, coef);
     return check_hip(hipGetLastError(), "hybrid projected solve");
+}
+kct_status sk_hybrid_choose(double *S, const double *gk, double *work, double *coef, double *hist, int rule,
+                            double noise_level, hipStream_t st)
+{
+    SC1(k_hybrid_choose, dim3(1), dim3(256), 0, st, S, gk, work, coef, hist, rule, noise_level);
+    return check_hip(hipGetLastError(), "hybrid parameter choice");
 }
 
 } // namespace kct

@@ -17,10 +17,12 @@
 // parameter) read zero instead of leaving the buffer.
 //
 // Workgroups are renumbered so that the 8 XCDs (round-robin dispatch) each
-// take a contiguous block of angles: rays of one angle share the voxels they
-// cross, so each XCD's L2 holds one angle's working set.
+// take a contiguous range of the work order below, in which neighbouring
+// workgroups trace neighbouring angles and detector rows (see k_forward).
 
 #include "kct_internal.hpp"
+
+#include <algorithm>
 
 namespace kct {
 
@@ -75,36 +77,49 @@ __device__ inline double block_sum_256(double v, double *red)
     return s;
 }
 
-template <typename TV, typename TP, typename IDX>
-__global__ __launch_bounds__(256) void k_forward(const TV *__restrict__ vpad, TP *__restrict__ proj,
-                                                 const AngleGeo *__restrict__ tab, GeoParams g, PadLayout pl,
-                                                 int tiles_u, int tiles_v, int64_t groups, Epilogue ep)
-{
-    __shared__ double red[4];
-    const int64_t g8 = (groups + 7) / 8;
-    const int64_t b = blockIdx.x;
-    const int64_t logical = (b & 7) * g8 + (b >> 3);
-    if (logical >= groups) return;
-    if (ep.scal && ep.scal[S_DONE] != 0.0) return;
+constexpr int64_t FWD_MAX_BLOCKS = int64_t(1) << 20; // 2^28 work-items per dispatch
 
+// 0.0 or 1.0 from a predicate, built from the high word only (one select).
+__device__ inline double one_if(bool c)
+{
+    return __builtin_bit_cast(double, uint64_t(c ? 0x3ff00000u : 0u) << 32);
+}
+
+// Work order: angle blocks of FWD_AB angles; inside a block, detector row
+// bands of 4 rows; inside a band, the FWD_AB angles; inside an angle, the
+// 64-pixel u tiles.  The ~256 workgroups an XCD keeps in flight then cover a
+// few row bands of a handful of neighbouring angles, whose rays cross the
+// same few z-slices of the volume: that working set fits the XCD's 4 MB L2.
+constexpr int FWD_AB = 8;
+
+// One 64 x 4 ray tile (logical workgroup index `logical`).
+template <typename TV, typename TP, typename OFF, bool PREFETCH>
+__device__ inline void fwd_tile(const TV *__restrict__ vpad, TP *__restrict__ proj, const AngleGeo *__restrict__ tab,
+                                const GeoParams &g, const PadLayout &pl, int tiles_u, int tiles_v, int64_t logical,
+                                const Epilogue &ep, double *red)
+{
     double c0 = ep.c[0], c1 = ep.c[1];
     if (ep.coef_idx >= 0) {
         c0 = ep.scal[ep.coef_idx];
         c1 = ep.scal[ep.coef_idx + 1];
     }
 
-    const int per_angle = tiles_u * tiles_v;
-    const int a = int(logical / per_angle);
-    const int rem = int(logical - int64_t(a) * per_angle);
-    const int tvi = rem / tiles_u, tui = rem - tvi * tiles_u;
+    const int per_band = FWD_AB * tiles_u;
+    const int per_block = per_band * tiles_v;
+    const int ab = int(logical / per_block);
+    const int r1 = int(logical - int64_t(ab) * per_block);
+    const int tvi = r1 / per_band;
+    const int r2 = r1 - tvi * per_band;
+    const int ai = r2 / tiles_u, tui = r2 - ai * tiles_u;
+    const int a = ab * FWD_AB + ai;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int iu = tui * FWD_TU + lane, iv = tvi * FWD_TV + wv;
-    const bool valid = iu < g.nu && iv < g.nv;
+    const bool valid = a < g.na && iu < g.nu && iv < g.nv;
 
-    const AngleGeo A = tab[a];
     float acc = 0.f;
     double dn = 0.0;
     if (valid) {
+        const AngleGeo A = tab[a];
         const double u = (iu - g.cu) * g.du, v = (iv - g.cv) * g.dv;
         const double dx = A.d0x + u * A.eux, dy = A.d0y + u * A.euy, dz = v * g.ivz;
         dn = sqrt(g.dsd * g.dsd + u * u + v * v);
@@ -138,36 +153,86 @@ __global__ __launch_bounds__(256) void k_forward(const TV *__restrict__ vpad, TP
             const int i = min(max(int(floor(A.svx + tmin * dx)), 0), g.nx - 1);
             const int j = min(max(int(floor(A.svy + tmin * dy)), 0), g.ny - 1);
             const int k = min(max(int(floor(A.svz + tmin * dz)), 0), g.nz - 1);
-            // Element strides of the chosen padded copy.
-            const int64_t sx = A.transposed ? pl.py : 1;
-            const int64_t sy = A.transposed ? 1 : pl.px;
-            const int64_t sz = pl.px * pl.py;
-            const int64_t base = A.transposed ? pl.vox : 0;
+            // Byte strides of the chosen padded copy.
+            constexpr int64_t ES = sizeof(TV);
+            const int64_t sx = (A.transposed ? pl.py : 1) * ES;
+            const int64_t sy = (A.transposed ? 1 : pl.px) * ES;
+            const int64_t sz = pl.px * pl.py * ES;
+            const int64_t base = (A.transposed ? pl.vox : 0) * ES;
             constexpr double FAR = 1.0e300;
             double tx = FAR, ty = FAR, tz = FAR, dtx = 0.0, dty = 0.0, dtz = 0.0;
-            IDX stx = 0, sty = 0, stz = 0;
-            if (dx > 0.0) { tx = (i + 1 - A.svx) * inx; dtx = inx; stx = IDX(sx); }
-            else if (dx < 0.0) { tx = (i - A.svx) * inx; dtx = -inx; stx = IDX(-sx); }
-            if (dy > 0.0) { ty = (j + 1 - A.svy) * iny; dty = iny; sty = IDX(sy); }
-            else if (dy < 0.0) { ty = (j - A.svy) * iny; dty = -iny; sty = IDX(-sy); }
-            if (dz > 0.0) { tz = (k + 1 - A.svz) * inz; dtz = inz; stz = IDX(sz); }
-            else if (dz < 0.0) { tz = (k - A.svz) * inz; dtz = -inz; stz = IDX(-sz); }
-            IDX idx = IDX(base + (i + 1) * sx + (j + 1) * sy + (k + 1) * sz);
+            OFF stx = 0, sty = 0, stz = 0;
+            if (dx > 0.0) { tx = (i + 1 - A.svx) * inx; dtx = inx; stx = OFF(sx); }
+            else if (dx < 0.0) { tx = (i - A.svx) * inx; dtx = -inx; stx = OFF(-sx); }
+            if (dy > 0.0) { ty = (j + 1 - A.svy) * iny; dty = iny; sty = OFF(sy); }
+            else if (dy < 0.0) { ty = (j - A.svy) * iny; dty = -iny; sty = OFF(-sy); }
+            if (dz > 0.0) { tz = (k + 1 - A.svz) * inz; dtz = inz; stz = OFF(sz); }
+            else if (dz < 0.0) { tz = (k - A.svz) * inz; dtz = -inz; stz = OFF(-sz); }
+            OFF off = OFF(base + (i + 1) * sx + (j + 1) * sy + (k + 1) * sz);
+            const char *vb = reinterpret_cast<const char *>(vpad);
             double tc = tmin;
-            // A ray crosses at most nx+ny+nz+3 planes; the cap only guarantees
-            // termination if rounding ever produced a non-advancing step.
-            int guard = g.nx + g.ny + g.nz + 8;
-            do {
-                const double tn = fmin(fmin(tx, ty), fmin(tz, tmax));
-                const float val = to_f32(vpad[idx]);
-                acc = fmaf(float(tn - tc), val, acc);
-                tc = tn;
-                const bool cx = tx <= tn, cy = ty <= tn, cz = tz <= tn;
-                tx = cx ? tx + dtx : tx;
-                ty = cy ? ty + dty : ty;
-                tz = cz ? tz + dtz : tz;
-                idx += (cx ? stx : IDX(0)) + (cy ? sty : IDX(0)) + (cz ? stz : IDX(0));
-            } while (tc < tmax && --guard > 0);
+            // Termination: while tc < tmax, the nearest crossing tn is one of
+            // tx, ty, tz (all >= tc) and that axis then advances by its
+            // step 1/|d| >= v/|pixel - source| > 0, so tc reaches tmax after at
+            // most nx+ny+nz+3 crossings.  Every access stays inside the padded
+            // copy: indices start inside the volume and at most one step per
+            // axis can land on the zero border before tc reaches tmax.
+            if constexpr (PREFETCH) {
+                // Two segments per trip, so the voxel value is requested a
+                // whole step before its FMA and no register is copied.  Each
+                // step advances exactly one axis, the one whose crossing comes
+                // first (x before y before z on ties; a tie then yields a
+                // zero-length segment in a diagonal neighbour, which adds
+                // exactly 0).  A lane whose next crossing lies at or beyond
+                // tmax adds its last segment, up to tmax, and leaves the loop.
+                float va = to_f32(*reinterpret_cast<const TV *>(vb + off));
+                for (;;) {
+                    const double m1 = fmin(tx, ty);
+                    const double t1 = fmin(m1, tz);
+                    if (!(t1 < tmax)) {
+                        acc = fmaf(float(tmax - tc), va, acc);
+                        break;
+                    }
+                    {
+                        const bool xy = tx <= ty, first = m1 <= tz;
+                        tx = fma(one_if(xy && first), dtx, tx);
+                        ty = fma(one_if(!xy && first), dty, ty);
+                        tz = fma(one_if(!first), dtz, tz);
+                        off += first ? (xy ? stx : sty) : stz;
+                    }
+                    const float vb1 = to_f32(*reinterpret_cast<const TV *>(vb + off));
+                    acc = fmaf(float(t1 - tc), va, acc);
+                    const double m2 = fmin(tx, ty);
+                    const double t2 = fmin(m2, tz);
+                    if (!(t2 < tmax)) {
+                        acc = fmaf(float(tmax - t1), vb1, acc);
+                        break;
+                    }
+                    {
+                        const bool xy = tx <= ty, first = m2 <= tz;
+                        tx = fma(one_if(xy && first), dtx, tx);
+                        ty = fma(one_if(!xy && first), dty, ty);
+                        tz = fma(one_if(!first), dtz, tz);
+                        off += first ? (xy ? stx : sty) : stz;
+                    }
+                    va = to_f32(*reinterpret_cast<const TV *>(vb + off));
+                    acc = fmaf(float(t2 - t1), vb1, acc);
+                    tc = t2;
+                }
+            } else {
+                for (;;) {
+                    const double tn = fmin(fmin(tx, ty), fmin(tz, tmax));
+                    const float val = to_f32(*reinterpret_cast<const TV *>(vb + off));
+                    acc = fmaf(float(tn - tc), val, acc);
+                    tc = tn;
+                    if (!(tc < tmax)) break;
+                    const bool cx = tx <= tn, cy = ty <= tn, cz = tz <= tn;
+                    tx = fma(one_if(cx), dtx, tx);
+                    ty = fma(one_if(cy), dty, ty);
+                    tz = fma(one_if(cz), dtz, tz);
+                    off += (cx ? stx : OFF(0)) + (cy ? sty : OFF(0)) + (cz ? stz : OFF(0));
+                }
+            }
         }
     }
 
@@ -175,7 +240,7 @@ __global__ __launch_bounds__(256) void k_forward(const TV *__restrict__ vpad, TP
     if (valid) {
         const int64_t ray = (int64_t(a) * g.nv + iv) * g.nu + iu;
         double o = c0 * (double(acc) * dn);
-        if (ep.in1) o += c1 * double(to_f32(static_cast<const TP *>(ep.in1)[ray]));
+        if (ep.in1 && c1 != 0.0) o += c1 * double(to_f32(static_cast<const TP *>(ep.in1)[ray]));
         const TP st = from_f32<TP>(float(o));
         proj[ray] = st;
         outv = to_f32(st);
@@ -183,6 +248,29 @@ __global__ __launch_bounds__(256) void k_forward(const TV *__restrict__ vpad, TP
     if (ep.partials) {
         const double s = block_sum_256(double(outv) * double(outv), red);
         if (threadIdx.x == 0) ep.partials[logical] = s;
+    }
+}
+
+// A dispatch holds fewer than 2^32 work-items, so large problems launch at
+// most FWD_MAX_BLOCKS workgroups (a multiple of 8) and each takes the tiles
+// blockIdx.x, blockIdx.x + gridDim.x, ...  The physical index b keeps its XCD
+// (b mod 8) on every pass; the logical tile is (b mod 8) * g8 + b / 8, so each
+// XCD works through one contiguous eighth of the tiles (neighbouring angles
+// and detector rows share its L2).
+template <typename TV, typename TP, typename OFF, bool PREFETCH>
+__global__ __launch_bounds__(256) void k_forward(const TV *__restrict__ vpad, TP *__restrict__ proj,
+                                                 const AngleGeo *__restrict__ tab, GeoParams g, PadLayout pl,
+                                                 int tiles_u, int tiles_v, int64_t groups, int64_t launch,
+                                                 Epilogue ep)
+{
+    __shared__ double red[4];
+    if (ep.scal && ep.scal[S_DONE] != 0.0) return;
+    const int64_t g8 = (groups + 7) / 8;
+    for (int64_t b = blockIdx.x; b < launch; b += gridDim.x) {
+        const int64_t logical = (b & 7) * g8 + (b >> 3);
+        if (logical >= groups) continue;
+        fwd_tile<TV, TP, OFF, PREFETCH>(vpad, proj, tab, g, pl, tiles_u, tiles_v, logical, ep, red);
+        __syncthreads(); // red[] is reused by the next tile's reduction
     }
 }
 
@@ -200,18 +288,22 @@ template <typename TV, typename TP>
 kct_status fwd_typed(Plan &p, const void *pad, void *proj, const Epilogue &ep, hipStream_t st)
 {
     const int tiles_u = (p.gp.nu + FWD_TU - 1) / FWD_TU, tiles_v = (p.gp.nv + FWD_TV - 1) / FWD_TV;
-    const int64_t groups = int64_t(p.gp.na) * tiles_u * tiles_v;
+    const int64_t groups = fwd_num_groups(p);
     const int64_t launch = ((groups + 7) / 8) * 8;
-    if (launch > int64_t(0x7fffffff)) return fail(KCT_E_GEOMETRY, "forward projection grid too large");
-    const bool small = 2 * p.pad.vox < int64_t(0xffffffffLL);
-    if (small)
-        hipLaunchKernelGGL((k_forward<TV, TP, uint32_t>), dim3(unsigned(launch)), dim3(256), 0, st,
-                           static_cast<const TV *>(pad), static_cast<TP *>(proj), p.d_tab, p.gp, p.pad,
-                           tiles_u, tiles_v, groups, ep);
-    else
-        hipLaunchKernelGGL((k_forward<TV, TP, uint64_t>), dim3(unsigned(launch)), dim3(256), 0, st,
-                           static_cast<const TV *>(pad), static_cast<TP *>(proj), p.d_tab, p.gp, p.pad,
-                           tiles_u, tiles_v, groups, ep);
+    const unsigned grid = unsigned(std::min<int64_t>(launch, FWD_MAX_BLOCKS));
+    // 32-bit byte offsets when both padded copies fit in 4 GiB.
+    const bool small = 2 * p.pad.vox * int64_t(sizeof(TV)) < int64_t(0xffffffffLL);
+#define KCT_FWD_LAUNCH(OFF_T, PF)                                                                                  \
+    hipLaunchKernelGGL((k_forward<TV, TP, OFF_T, PF>), dim3(grid), dim3(256), 0, st, static_cast<const TV *>(pad), \
+                       static_cast<TP *>(proj), p.d_tab, p.gp, p.pad, tiles_u, tiles_v, groups, launch, ep)
+    if (small) {
+        if (p.fwd_prefetch) KCT_FWD_LAUNCH(uint32_t, true);
+        else KCT_FWD_LAUNCH(uint32_t, false);
+    } else {
+        if (p.fwd_prefetch) KCT_FWD_LAUNCH(uint64_t, true);
+        else KCT_FWD_LAUNCH(uint64_t, false);
+    }
+#undef KCT_FWD_LAUNCH
     return check_hip(hipGetLastError(), "forward projection launch");
 }
 
@@ -266,7 +358,8 @@ kct_status launch_pad_volume_as(Plan &p, const void *vol, int in_dtype, int out_
 int64_t fwd_num_groups(const Plan &p)
 {
     const int tiles_u = (p.gp.nu + FWD_TU - 1) / FWD_TU, tiles_v = (p.gp.nv + FWD_TV - 1) / FWD_TV;
-    return int64_t(p.gp.na) * tiles_u * tiles_v;
+    const int64_t blocks = (p.gp.na + FWD_AB - 1) / FWD_AB;
+    return blocks * FWD_AB * tiles_u * tiles_v;
 }
 
 // Project the padded copies in `pad` (built by launch_pad_volume with

@@ -18,7 +18,13 @@
 //           inner CGLS on [A; lam L D]: q1 = A p -> ||q1||^2 and
 //           ||lam L D p||^2; alpha; r1 -= alpha q1; r2 -= alpha lam L D p;
 //           s = A^T r1 + lam D^T L r2 -> ||s||^2; beta; x, p updates
+//   AB-GMRES (Sec. 2.1.4) z = B V_j; V_{j+1} = A z; modified Gram-Schmidt
+//           against V_1..V_j (dot, scalar, axpy per vector); normalise;
+//           Givens update of H and of the residual.  At the end
+//           x = B (sum_i y_i V_i).  BA-GMRES: t = A V_j; V_{j+1} = B t; ...;
+//           x = sum_i y_i V_i.
 
+#include "gmres.hpp"
 #include "krylov.hpp"
 
 #include <cmath>
@@ -39,7 +45,9 @@ struct Layout {
     int64_t nparts = 0;
 };
 
-bool solver_ok(int s) { return s >= KCT_CGLS && s <= KCT_IRN_TV_CGLS; }
+bool solver_ok(int s) { return s >= KCT_CGLS && s <= KCT_BA_GMRES; }
+
+bool is_gmres(int s) { return s == KCT_AB_GMRES || s == KCT_BA_GMRES; }
 
 kct_status check_params(const kct_solve_params *prm)
 {
@@ -53,6 +61,24 @@ kct_status check_params(const kct_solve_params *prm)
     if (prm->n_iter < 0 || prm->n_iter > 100000) return fail(KCT_E_INVALID_ARG, "n_iter out of range");
     if (!(prm->lambda >= 0.0) || !std::isfinite(prm->lambda)) return fail(KCT_E_INVALID_ARG, "lambda must be >= 0");
     if (!dtype_ok(prm->vec_dtype)) return fail(KCT_E_DTYPE, "unknown vector storage type");
+    if (prm->backprojector != KCT_BP_MATCHED) {
+        if (prm->backprojector != KCT_BP_INTERP) return fail(KCT_E_INVALID_ARG, "unknown back projector");
+        if (!is_gmres(prm->solver))
+            return fail(KCT_E_INVALID_ARG, "only AB- and BA-GMRES take an unmatched back projector");
+    }
+    if (is_gmres(prm->solver)) {
+        if (prm->lambda != 0.0) return fail(KCT_E_INVALID_ARG, "AB-/BA-GMRES solve the undamped problem (lambda 0)");
+        // Unit basis vectors have entries near 1/sqrt(n): below FP16's normal range.
+        if (prm->vec_dtype == KCT_F16) return fail(KCT_E_DTYPE, "AB-/BA-GMRES store their basis in FP32 or BF16");
+    }
+    if (prm->lambda_rule != KCT_LAMBDA_FIXED) {
+        if (prm->lambda_rule != KCT_LAMBDA_GCV && prm->lambda_rule != KCT_LAMBDA_DP)
+            return fail(KCT_E_INVALID_ARG, "unknown lambda rule");
+        if (prm->solver != KCT_HYBRID_LSQR)
+            return fail(KCT_E_INVALID_ARG, "only hybrid LSQR chooses lambda during the iterations");
+        if (prm->lambda_rule == KCT_LAMBDA_DP && !(prm->noise_level > 0.0 && std::isfinite(prm->noise_level)))
+            return fail(KCT_E_INVALID_ARG, "the discrepancy principle needs a noise level > 0");
+    }
     return KCT_OK;
 }
 
@@ -61,7 +87,8 @@ Layout layout(const Plan &p, const kct_solve_params &prm)
     Layout L;
     const int64_t N = p.n_ray(), M = p.n_vox();
     const size_t vt = dtype_size(prm.vec_dtype);
-    L.nparts = std::max<int64_t>({fwd_num_groups(p), bwd_num_groups(p), int64_t(VEC_GROUPS)});
+    L.nparts = std::max<int64_t>({fwd_num_groups(p), bwd_num_groups(p), ibp_num_groups(p), int64_t(VEC_GROUPS),
+                                  int64_t(GM_GROUPS)});
     size_t o = 0;
     L.scal = o; o += up(sizeof(double) * S_COUNT);
     L.pa = o; o += up(sizeof(double) * L.nparts);
@@ -92,9 +119,22 @@ Layout layout(const Plan &p, const kct_solve_params &prm)
         L.v[0] = o; o += up(size_t(N) * vt);                 // U
         L.v[1] = o; o += up(size_t(M) * vt * size_t(k + 1)); // basis V_1..V_{k+1}
         L.gk = o; o += up(sizeof(double) * (2 * size_t(k) + 4));
-        L.work = o; o += up(sizeof(double) * (2 * size_t(k) + 1) * (size_t(k) + 1));
+        // QR of [B_k; lam I] (fixed lambda) or W, Q, sigma, c, y of the SVD (GCV, DP).
+        L.work = o; o += up(sizeof(double) * ((2 * size_t(k) + 1) * (size_t(k) + 1) + 4 * size_t(k) + 8));
         L.coef = o; o += up(sizeof(double) * (size_t(k) + 1));
         break;
+    case KCT_AB_GMRES:
+    case KCT_BA_GMRES: {
+        const bool ab = prm.solver == KCT_AB_GMRES;
+        const int64_t nb = ab ? N : M, nt = ab ? M : N;
+        L.v[0] = o; o += up(size_t(nb) * vt * size_t(k + 1)); // basis V_1..V_{k+1}
+        L.v[1] = o; o += up(size_t(nt) * vt);                 // B V_j (AB) or A V_j (BA)
+        if (ab) { L.v[2] = o; o += up(size_t(N) * 4); }       // sum_i y_i V_i before the last B
+        L.gk = o; o += up(sizeof(double) * (size_t(k) + 1) * size_t(std::max(k, 1))); // H
+        L.work = o; o += up(sizeof(double) * (3 * size_t(k) + 2));                   // cs, sn, g
+        L.coef = o; o += up(sizeof(double) * (size_t(k) + 1));
+        break;
+    }
     case KCT_IRN_TV_CGLS:
         L.v[0] = o; o += up(size_t(N) * vt);    // r1
         L.v[1] = o; o += up(size_t(N) * vt);    // q1
@@ -206,7 +246,9 @@ kct_status gk_init(kct_state &s, void *V, double *gk)
     Plan &p = *s.plan;
     KCT_TRY(vk_fill(s.x, KCT_F32, s.M(), 0.f, s.st));
     KCT_TRY(vk_scale(s.b, KCT_F32, s.v(0), s.vt(), s.N(), nullptr, -1, s.pa(), s.st)); // U = b
-    KCT_TRY(sk_gk_init1(s.S(), red(s, s.pa(), vk_groups(s.N()), 0), s.prm.lambda, s.prm.n_iter, s.st));
+    // LSQR's damping; hybrid LSQR with a lambda rule recurs undamped quantities.
+    const double lam = s.prm.lambda_rule == KCT_LAMBDA_FIXED ? s.prm.lambda : 0.0;
+    KCT_TRY(sk_gk_init1(s.S(), red(s, s.pa(), vk_groups(s.N()), 0), lam, s.prm.n_iter, s.st));
     Epilogue eb;
     eb.scal = s.S();
     eb.coef_idx = S_B0; // V = A^T U / beta_1
@@ -275,14 +317,20 @@ kct_status hybrid_iter(kct_state &s)
 {
     const int k = s.enqueued;
     KCT_TRY(gk_step(s, basis_slot(s, k), basis_slot(s, k + 1)));
-    return sk_lsqr_alpha(s.S(), red(s, s.pa(), bwd_num_groups(*s.plan), 0), s.hist, gk_arr(s), s.st);
+    KCT_TRY(sk_lsqr_alpha(s.S(), red(s, s.pa(), bwd_num_groups(*s.plan), 0), s.hist, gk_arr(s), s.st));
+    if (s.prm.lambda_rule == KCT_LAMBDA_FIXED) return KCT_OK;
+    // lambda_k for this iteration: SVD of B_k, the rule's search, y_k.
+    double *work = reinterpret_cast<double *>(s.ws + s.L.work);
+    double *coef = reinterpret_cast<double *>(s.ws + s.L.coef);
+    return sk_hybrid_choose(s.S(), gk_arr(s), work, coef, s.hist, s.prm.lambda_rule, s.prm.noise_level, s.st);
 }
 
 kct_status hybrid_finish(kct_state &s)
 {
     double *work = reinterpret_cast<double *>(s.ws + s.L.work);
     double *coef = reinterpret_cast<double *>(s.ws + s.L.coef);
-    KCT_TRY(sk_hybrid_solve(s.S(), gk_arr(s), work, coef, s.st));
+    // With GCV or DP the last iteration already left y_k in coef.
+    if (s.prm.lambda_rule == KCT_LAMBDA_FIXED) KCT_TRY(sk_hybrid_solve(s.S(), gk_arr(s), work, coef, s.st));
     return vk_combine(s.x, s.v(1), s.vt(), s.M(), coef, s.S(), s.st);
 }
 
@@ -316,7 +364,7 @@ kct_status irn_begin_outer(kct_state &s, int outer)
     KCT_TRY(launch_backward(p, s.v(0), s.vt(), s.v(3), s.vt(), eb, s.st)); // s = A^T r1
     KCT_TRY(tv_adjoint_add(p, s.v(3), s.vt(), tv_r2(s), tv_w(s), lam, nullptr, s.pa(), s.st));
     KCT_TRY(vk_scale(s.v(3), s.vt(), s.v(2), s.vt(), s.M(), nullptr, -1, nullptr, s.st)); // p = s
-    return sk_tv_restart(s.S(), red(s, s.pa(), tv_num_groups(s.M()), 0), outer == 0, s.total, s.st);
+    return sk_tv_restart(s.S(), red(s, s.pa(), tv_num_groups(s.M()), 0), outer == 0, s.total, s.prm.lambda, s.st);
 }
 
 kct_status irn_init(kct_state &s)
@@ -350,6 +398,84 @@ kct_status irn_iter(kct_state &s)
     return KCT_OK;
 }
 
+// ---------------------------------------------------------------- AB-/BA-GMRES
+bool gm_ab(const kct_state &s) { return s.prm.solver == KCT_AB_GMRES; }
+int64_t gm_n(const kct_state &s) { return gm_ab(s) ? s.N() : s.M(); } // basis vector length
+int gm_ldh(const kct_state &s) { return s.prm.n_iter + 1; }
+double *gm_H(kct_state &s) { return reinterpret_cast<double *>(s.ws + s.L.gk); }
+double *gm_cs(kct_state &s) { return reinterpret_cast<double *>(s.ws + s.L.work); }
+double *gm_sn(kct_state &s) { return gm_cs(s) + s.prm.n_iter; }
+double *gm_g(kct_state &s) { return gm_sn(s) + s.prm.n_iter; }
+void *gm_V(kct_state &s, int i) { return static_cast<char *>(s.v(0)) + size_t(i) * size_t(gm_n(s)) * dtype_size(s.vt()); }
+
+// y = B x with the solver's back projector; the partial sums of y^2 per
+// workgroup go to ep.partials.
+kct_status apply_B(kct_state &s, const void *proj, int pdt, void *vol, int vdt, const Epilogue &ep)
+{
+    if (s.prm.backprojector == KCT_BP_INTERP) return launch_interp_backward(*s.plan, proj, pdt, vol, vdt, ep, s.st);
+    return launch_backward(*s.plan, proj, pdt, vol, vdt, ep, s.st);
+}
+
+int64_t B_groups(const kct_state &s)
+{
+    return s.prm.backprojector == KCT_BP_INTERP ? ibp_num_groups(*s.plan) : bwd_num_groups(*s.plan);
+}
+
+kct_status gm_init(kct_state &s)
+{
+    KCT_TRY(vk_fill(s.x, KCT_F32, s.M(), 0.f, s.st));
+    void *V0 = gm_V(s, 0);
+    Reduced r0;
+    if (gm_ab(s)) { // r0 = b
+        KCT_TRY(vk_scale(s.b, KCT_F32, V0, s.vt(), s.N(), nullptr, -1, s.pa(), s.st));
+        r0 = red(s, s.pa(), vk_groups(s.N()), 0);
+    } else { // r0 = B b
+        Epilogue ep;
+        ep.partials = s.pa();
+        KCT_TRY(apply_B(s, s.b, KCT_F32, V0, s.vt(), ep));
+        r0 = red(s, s.pa(), B_groups(s), 0);
+    }
+    KCT_TRY(gm_sc_init(s.S(), r0.ptr, r0.n, gm_g(s), s.prm.n_iter, s.st));
+    return gm_scale(V0, s.vt(), gm_n(s), s.S(), S_V0, s.st);
+}
+
+kct_status gm_iter(kct_state &s)
+{
+    const int j = s.enqueued, ldh = gm_ldh(s);
+    const int64_t n = gm_n(s);
+    void *Vj = gm_V(s, j), *W = gm_V(s, j + 1);
+    Epilogue plain;
+    if (gm_ab(s)) {
+        KCT_TRY(apply_B(s, Vj, s.vt(), s.v(1), s.vt(), plain)); // z = B V_j
+        KCT_TRY(forward_into(s, s.v(1), W, plain));             // W = A z
+    } else {
+        KCT_TRY(forward_into(s, Vj, s.v(1), plain));            // t = A V_j
+        KCT_TRY(apply_B(s, s.v(1), s.vt(), W, s.vt(), plain)); // W = B t
+    }
+    for (int i = 0; i <= j; ++i) { // modified Gram-Schmidt
+        KCT_TRY(gm_dot(W, gm_V(s, i), s.vt(), n, s.pa(), s.st));
+        const Reduced h = red(s, s.pa(), gm_num_groups(n), 0);
+        KCT_TRY(gm_sc_h(s.S(), h.ptr, h.n, gm_H(s), i, j, ldh, s.st));
+        KCT_TRY(gm_axpy(W, gm_V(s, i), s.vt(), n, s.S(), S_P0, s.st));
+    }
+    KCT_TRY(gm_dot(W, W, s.vt(), n, s.pa(), s.st));
+    const Reduced w2 = red(s, s.pa(), gm_num_groups(n), 0);
+    KCT_TRY(gm_sc_norm(s.S(), w2.ptr, w2.n, gm_H(s), j, ldh, s.st));
+    KCT_TRY(gm_scale(W, s.vt(), n, s.S(), S_V0, s.st));
+    return gm_sc_givens(s.S(), gm_H(s), gm_cs(s), gm_sn(s), gm_g(s), j, ldh, s.hist, s.st);
+}
+
+kct_status gm_finish(kct_state &s)
+{
+    double *coef = reinterpret_cast<double *>(s.ws + s.L.coef);
+    KCT_TRY(gm_sc_solve(s.S(), gm_H(s), gm_g(s), coef, gm_ldh(s), s.st));
+    if (!gm_ab(s)) return vk_combine(s.x, s.v(0), s.vt(), s.M(), coef, s.S(), s.st);
+    float *z = static_cast<float *>(s.v(2));
+    KCT_TRY(vk_combine(z, s.v(0), s.vt(), s.N(), coef, s.S(), s.st)); // sum_i y_i V_i
+    Epilogue plain;
+    return apply_B(s, z, KCT_F32, s.x, KCT_F32, plain);                 // x = B (...)
+}
+
 kct_status enqueue_init(kct_state &s)
 {
     switch (s.prm.solver) {
@@ -358,6 +484,8 @@ kct_status enqueue_init(kct_state &s)
     case KCT_LSMR: return lsmr_init(s);
     case KCT_HYBRID_LSQR: return hybrid_init(s);
     case KCT_IRN_TV_CGLS: return irn_init(s);
+    case KCT_AB_GMRES:
+    case KCT_BA_GMRES: return gm_init(s);
     }
     return fail(KCT_E_INVALID_ARG, "unknown solver");
 }
@@ -370,6 +498,8 @@ kct_status enqueue_iter(kct_state &s)
     case KCT_LSMR: return lsmr_iter(s);
     case KCT_HYBRID_LSQR: return hybrid_iter(s);
     case KCT_IRN_TV_CGLS: return irn_iter(s);
+    case KCT_AB_GMRES:
+    case KCT_BA_GMRES: return gm_iter(s);
     }
     return fail(KCT_E_INVALID_ARG, "unknown solver");
 }
@@ -438,6 +568,7 @@ kct_status kct_state_step(kct_state *s, int32_t n_steps)
     }
     if (s->enqueued == s->total && !s->finalized) {
         if (s->prm.solver == KCT_HYBRID_LSQR) KCT_TRY(hybrid_finish(*s));
+        if (is_gmres(s->prm.solver)) KCT_TRY(gm_finish(*s));
         s->finalized = true;
     }
     return KCT_OK;

@@ -131,7 +131,7 @@ __global__ __launch_bounds__(256) void k_tv_adjoint_add(T *__restrict__ s, const
 
 // IRN restart of CGLS: gamma = ||s||^2, fresh Krylov space.
 __global__ __launch_bounds__(256) void k_sc_tv_restart(double *S, const double *ps, int64_t ns, int first,
-                                                       int n_rows)
+                                                       int n_rows, double lam)
 {
     double s2 = 0.0;
     for (int64_t e = threadIdx.x; e < ns; e += 256) s2 += ps[e];
@@ -142,6 +142,7 @@ __global__ __launch_bounds__(256) void k_sc_tv_restart(double *S, const double *
         S[S_ITER] = n_rows;
         S[S_RES] = 0.0;
         S[S_DONE] = 0.0;
+        S[S_HLAM] = lam;
     }
     if (S[S_DONE] != 2.0) S[S_DONE] = (s2 == s2 && s2 - s2 == 0.0) ? (s2 > 0.0 ? 0.0 : 1.0) : 2.0;
     S[S_GAMMA] = s2;
@@ -223,9 +224,9 @@ kct_status tv_adjoint_add(const Plan &p, void *s, int dt, const float *r2, const
 
 int tv_num_groups(int64_t M) { return tv_groups(M); }
 
-kct_status sk_tv_restart(double *S, Reduced s, bool first, int n_rows, hipStream_t st)
+kct_status sk_tv_restart(double *S, Reduced s, bool first, int n_rows, double lam, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_sc_tv_restart, dim3(1), dim3(256), 0, st, S, s.ptr, s.n, first ? 1 : 0, n_rows);
+    hipLaunchKernelGGL(k_sc_tv_restart, dim3(1), dim3(256), 0, st, S, s.ptr, s.n, first ? 1 : 0, n_rows, lam);
     return check_hip(hipGetLastError(), "tv restart scalars");
 }
 

@@ -34,8 +34,8 @@ import math
 import numpy as np
 
 __all__ = ["angles", "workload", "geometry", "crop_geometry", "ellipsoid_phantom", "torso_phantom",
-           "porous_phantom", "phantom", "add_noise", "random_volume", "random_projections",
-           "serve_stream", "WORKLOADS"]
+           "porous_phantom", "phantom", "add_noise", "add_noise_torch", "random_volume", "random_projections",
+           "serve_stream", "block_geometry", "WORKLOADS"]
 
 
 def angles(n: int, span: float = 2.0 * math.pi, start: float = 0.0) -> np.ndarray:
@@ -96,6 +96,19 @@ def crop_geometry(name: str, n_vox: int, n_det: int, n_angles: int) -> dict:
     g = dict(WORKLOADS[name]["geom"])
     g.update(nx=n_vox, ny=n_vox, nz=n_vox, nu=n_det, nv=n_det, n_angles=n_angles)
     return geometry(g)
+
+
+def block_geometry(g: dict, origin, shape) -> dict:
+    """The sub-grid of geometry ``g`` that starts at voxel ``origin`` (k, j, i)
+    and has ``shape`` (nz, ny, nx): same voxel size, same place in space, same
+    source, detector and angles."""
+    (k0, j0, i0), (bz, by, bx) = origin, shape
+    b = dict(g)
+    b.update(nx=bx, ny=by, nz=bz,
+             ox=g["ox"] + (i0 + bx / 2 - g["nx"] / 2) * g["vx"],
+             oy=g["oy"] + (j0 + by / 2 - g["ny"] / 2) * g["vy"],
+             oz=g["oz"] + (k0 + bz / 2 - g["nz"] / 2) * g["vz"])
+    return b
 
 
 def _haar_rotation(rng) -> np.ndarray:
@@ -259,6 +272,29 @@ def add_noise(b_clean, spec: dict, seed: int) -> tuple[np.ndarray, dict]:
     else:
         raise ValueError(spec["kind"])
     return out.astype(np.float32), info
+
+
+def add_noise_torch(b_clean, spec: dict, seed: int):
+    """``add_noise`` for a torch tensor, drawn on the tensor's device (for
+    projections too large to round-trip through host memory).  Same model,
+    different random stream (torch's generator)."""
+    import torch
+
+    gen = torch.Generator(device=b_clean.device).manual_seed(seed + 1000)
+    info = {}
+    if spec["kind"] == "gaussian":
+        sig = spec["rel_sigma"] * float(b_clean.abs().max())
+        out = b_clean + sig * torch.randn(b_clean.shape, generator=gen, device=b_clean.device)
+    elif spec["kind"] == "poisson":
+        i0 = float(spec["i0"])
+        counts = torch.poisson(i0 * torch.exp(-b_clean.double()), generator=gen)
+        info["clamped_fraction"] = float((counts < 1.0).double().mean())
+        out = torch.log(i0 / counts.clamp_(min=1.0))
+    elif spec["kind"] == "none":
+        out = b_clean
+    else:
+        raise ValueError(spec["kind"])
+    return out.float().contiguous(), info
 
 
 def random_volume(shape, seed: int, lo: float = 0.0, hi: float = 1.0) -> np.ndarray:

@@ -40,12 +40,16 @@ def test_header_constants_match_binding():
     assert int(vals["KCT_CGLS"]) == _lib.KCT_CGLS and int(vals["KCT_LSMR"]) == _lib.KCT_LSMR
     assert int(vals["KCT_HYBRID_LSQR"]) == _lib.KCT_HYBRID_LSQR
     assert int(vals["KCT_IRN_TV_CGLS"]) == _lib.KCT_IRN_TV_CGLS
+    assert int(vals["KCT_LAMBDA_FIXED"]) == _lib.KCT_LAMBDA_FIXED and int(vals["KCT_LAMBDA_GCV"]) == _lib.KCT_LAMBDA_GCV
+    assert int(vals["KCT_LAMBDA_DP"]) == _lib.KCT_LAMBDA_DP
+    assert int(vals["KCT_AB_GMRES"]) == _lib.KCT_AB_GMRES and int(vals["KCT_BA_GMRES"]) == _lib.KCT_BA_GMRES
+    assert int(vals["KCT_BP_MATCHED"]) == _lib.KCT_BP_MATCHED and int(vals["KCT_BP_INTERP"]) == _lib.KCT_BP_INTERP
     assert int(re.search(r"#define KCT_HIST_COLS (\d+)", src).group(1)) == _lib.KCT_HIST_COLS
     for name, code in _lib.STATUS_NAMES.items():
         assert int(vals[code]) == name
     # struct layouts: ctypes sizes equal the C sizes under the x86-64 ABI
     assert ctypes.sizeof(_lib.KctGeometry) == 4 * 3 + 4 + 8 * 6 + 4 * 2 + 8 * 2 + 8 * 2 + 8 + 8
-    assert ctypes.sizeof(_lib.KctSolveParams) == 4 + 4 + 8 + 4 + 4 + 8 + 4 + 4
+    assert ctypes.sizeof(_lib.KctSolveParams) == 4 + 4 + 8 + 4 + 4 + 8 + 4 + 4 + 8 + 4 + 4
 
 
 def test_status_strings_and_version():
@@ -85,10 +89,11 @@ def test_invalid_geometry_rejected_without_device():
 def test_null_arguments_rejected():
     lib = _lib.load()
     n = ctypes.c_size_t()
-    p = _lib.KctSolveParams(0, 10, 0.0, 0, 0, 1e-3, 0, 0)
+    p = _lib.KctSolveParams(0, 10, 0.0, 0, 0, 1e-3, 0, 0, 0.0, 0, 0)
     assert lib.kct_solve_workspace_bytes(None, ctypes.byref(p), ctypes.byref(n)) == 1
     assert lib.kct_forward(None, None, 0, None, 0, None) == 1
     assert lib.kct_backproject(None, None, 0, None, 0, None) == 1
+    assert lib.kct_backproject_interp(None, None, 0, None, 0, None) == 1
     assert lib.kct_state_step(None, 1) == 1
     assert lib.kct_plan_destroy(None) == 0
     assert lib.kct_state_destroy(None) == 0

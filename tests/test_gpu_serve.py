@@ -75,7 +75,10 @@ def test_small_request_matches_oracle(stream):
     rng = np.random.default_rng(0)
 
     def perturbed(f):
-        return lambda z: (f(z) * (1 + 5e-7 * rng.standard_normal(f(z).shape))).astype(np.float32).astype(np.float64)
+        def g(z):
+            y = f(z)
+            return (y * (1 + 5e-7 * rng.standard_normal(y.shape))).astype(np.float32).astype(np.float64)
+        return g
 
     alt, _ = fn(perturbed(A), perturbed(AT), b, req.n_iter, req.lam)
     sens = np.linalg.norm(alt - ref) / np.linalg.norm(ref)

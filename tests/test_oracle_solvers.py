@@ -175,3 +175,138 @@ def test_breakdown_returns_zero():
         for fn in (S.cgls, S.lsqr, S.lsmr):
             x, _ = fn(Af, ATf, bn, 5)
             assert np.all(np.isfinite(x)) and np.linalg.norm(x) < 1e-6
+
+
+# ---- hybrid LSQR with a per-iteration parameter choice (Sec. 2.2.2) ---------
+
+def _full_gcv(A, b, lam):
+    """GCV of the full Tikhonov problem from its influence matrix
+    H = A (A^T A + lam^2 I)^-1 A^T: ||(I - H) b||^2 / tr(I - H)^2."""
+    n = A.shape[1]
+    H = A @ np.linalg.solve(A.T @ A + lam * lam * np.eye(n), A.T)
+    R = np.eye(A.shape[0]) - H
+    return float(np.linalg.norm(R @ b) ** 2 / np.trace(R) ** 2)
+
+
+def test_projected_gcv_equals_full_gcv():
+    """With A of size (n+1) x n and k = n Golub-Kahan steps, U_{n+1} is a
+    square orthogonal matrix, so the projected GCV function equals the full
+    problem's GCV function (residual and trace alike) for every lambda."""
+    A, b = _random_problem(m=7, n=6, cond=3.0, seed=4)
+    Af, ATf = _ops(A)
+    Us, Vs, B, beta1 = S.golub_kahan(Af, ATf, b, 6)
+    assert B.shape == (7, 6)
+    U = np.array(Us).T
+    assert np.abs(U.T @ U - np.eye(7)).max() < 1e-12  # the identity needs an orthogonal U
+    s, Q, c = S._projected_svd(B, beta1)
+    for lam in (1e-3, 0.02, 0.3, 1.0, 5.0):
+        assert S.gcv(s, c, lam) == pytest.approx(_full_gcv(A, b, lam), rel=1e-9)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_gcv_choice_is_the_grid_minimum(seed):
+    """The chosen lambda is at least as good as the best of 20001 brute-force
+    points over the search range, and never beaten by its neighbours."""
+    A, b = _ct_problem(seed)
+    Af, ATf = _ops(A)
+    for k in (3, 8, 15):
+        _, _, B, beta1 = S.golub_kahan(Af, ATf, b, k)
+        s, _, c = S._projected_svd(B, beta1)
+        lam = S.lambda_gcv(s, c)
+        L = math.log10(s[0])
+        brute = min(S.gcv(s, c, 10.0 ** g) for g in np.linspace(L - 7.0, L + 1.0, 20001))
+        g0 = S.gcv(s, c, lam)
+        assert g0 <= brute * (1 + 1e-9)
+        assert g0 <= S.gcv(s, c, lam * 1.001) and g0 <= S.gcv(s, c, lam / 1.001)
+
+
+def test_hybrid_dp_meets_discrepancy():
+    """Discrepancy principle: at every iteration where the target residual is
+    reachable, the full-space residual ||A x_k - b|| of the returned iterate
+    equals nl ||b||; before that, lambda_k = 0 and x_k is the LSQR iterate."""
+    A, _ = _random_problem(m=40, n=12, cond=10.0, seed=7)
+    rng = np.random.default_rng(7)
+    bc = A @ rng.standard_normal(12)
+    e = rng.standard_normal(40)
+    b = bc + 0.05 * np.linalg.norm(bc) / np.linalg.norm(e) * e
+    nl = 0.05 * np.linalg.norm(bc) / np.linalg.norm(b)
+    Af, ATf = _ops(A)
+    reached = 0
+    for k in range(1, 13):
+        x, h = S.hybrid_lsqr(Af, ATf, b, k, 0.0, rule="dp", noise_level=nl)
+        lam = h["lam"][-1]
+        r = np.linalg.norm(A @ x - b)
+        U = np.array(S.golub_kahan(Af, ATf, b, k)[0]).T
+        orth = np.abs(U.T @ U - np.eye(U.shape[1])).max()
+        if lam > 0:
+            # ||A x_k - b|| = ||B_k y_k - beta1 e1|| needs U_{k+1} orthonormal,
+            # which Golub-Kahan without reorthogonalisation keeps only so long.
+            if orth < 1e-8:
+                assert r == pytest.approx(nl * np.linalg.norm(b), rel=1e-8)
+                reached += 1
+        else:
+            xl, _ = S.lsqr(Af, ATf, b, k)
+            assert np.linalg.norm(x - xl) <= 1e-10 * np.linalg.norm(xl)
+            assert r >= nl * np.linalg.norm(b) * (1 - 1e-12)
+    assert reached >= 1
+
+
+def test_hybrid_rules_edge_cases():
+    A, b = _random_problem(seed=3)
+    Af, ATf = _ops(A)
+    # Noise level above 1: every lambda leaves the residual below the target, so the
+    # regularisation is infinite and x = 0.
+    x, h = S.hybrid_lsqr(Af, ATf, b, 5, 0.0, rule="dp", noise_level=1.5)
+    assert np.all(np.isinf(h["lam"])) and not np.any(x)
+    assert h["res"][-1] == pytest.approx(np.linalg.norm(b))
+    # A fixed lambda reproduces damped LSQR; GCV picks a finite positive value.
+    xf, hf = S.hybrid_lsqr(Af, ATf, b, 6, 0.7, rule="fixed")
+    xd, _ = S.lsqr(Af, ATf, b, 6, 0.7)
+    assert np.linalg.norm(xf - xd) <= 1e-10 * np.linalg.norm(xd)
+    _, hg = S.hybrid_lsqr(Af, ATf, b, 6, 0.0, rule="gcv")
+    assert np.all(np.isfinite(hg["lam"])) and np.all(hg["lam"] > 0)
+
+
+# ---- AB- and BA-GMRES (Sec. 2.1.4) ------------------------------------------
+
+def test_ab_ba_gmres_with_matched_backprojector():
+    """With B = A^T, AB-GMRES minimises ||b - A x|| over K_k(A^T A, A^T b)
+    (LSQR's iterate) and BA-GMRES minimises ||A^T (b - A x)|| over the same
+    space (LSMR's iterate)."""
+    A, b = _ct_problem(5)
+    Af, ATf = _ops(A)
+    for k in (1, 3, 7):
+        xa, ha = S.ab_gmres(Af, ATf, b, k)
+        xq, hq = S.lsqr(Af, ATf, b, k)
+        assert np.linalg.norm(xa - xq) <= 1e-9 * np.linalg.norm(xq)
+        assert ha["res"][-1] == pytest.approx(np.linalg.norm(b - A @ xq), rel=1e-9)
+        xb, hb = S.ba_gmres(Af, ATf, b, k)
+        xm, _ = S.lsmr(Af, ATf, b, k)
+        assert np.linalg.norm(xb - xm) <= 1e-9 * np.linalg.norm(xm)
+        assert hb["res"][-1] == pytest.approx(np.linalg.norm(A.T @ (b - A @ xm)), rel=1e-9)
+
+
+@pytest.mark.parametrize("k", [1, 2, 5])
+def test_gmres_krylov_optimality_unmatched(k):
+    """With a B that is not A^T, the iterates are the explicit minimisers over
+    explicitly built Krylov spaces: x = B y, y in K_k(AB, b) minimising
+    ||b - A B y|| (AB); x in K_k(BA, Bb) minimising ||B(b - A x)|| (BA)."""
+    A, b = _ct_problem(6)
+    rng = np.random.default_rng(k)
+    Bm = A.T * (1.0 + 0.2 * rng.standard_normal(A.T.shape))  # a perturbed back projector
+    Af, Bf = (lambda x: A @ x), (lambda y: Bm @ y)
+    xa, _ = S.ab_gmres(Af, Bf, b, k)
+    K = [b]
+    for _ in range(k - 1):
+        K.append(A @ (Bm @ K[-1]))
+    Q, _ = np.linalg.qr(np.array(K).T)
+    y, *_ = np.linalg.lstsq(A @ Bm @ Q, b, rcond=None)
+    xr = Bm @ (Q @ y)
+    assert np.linalg.norm(xa - xr) <= 1e-8 * np.linalg.norm(xr)
+    xb, _ = S.ba_gmres(Af, Bf, b, k)
+    K = [Bm @ b]
+    for _ in range(k - 1):
+        K.append(Bm @ (A @ K[-1]))
+    Q, _ = np.linalg.qr(np.array(K).T)
+    y, *_ = np.linalg.lstsq(Bm @ A @ Q, Bm @ b, rcond=None)
+    assert np.linalg.norm(xb - Q @ y) <= 1e-8 * np.linalg.norm(Q @ y)
