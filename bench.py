@@ -133,6 +133,58 @@ def counter_entry(kernel_key, digest):
     return k
 
 
+def _phantom_slab(job):
+    name, gd, k0, nz = job
+    import synth
+
+    g = dict(gd)
+    g["nz"] = nz
+    return k0, synth.phantom(name, g, full_n=gd["nx"], crop_origin=(k0, 0, 0))
+
+
+def phantom_in_slabs(name, gd, slab=100, workers=8):
+    """The workload's phantom, built in z-slabs by worker processes (each slab
+    equals the same block of the full phantom).  Call before the GPU is used."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
+    import numpy as np
+
+    out = np.empty((gd["nz"], gd["ny"], gd["nx"]), dtype=np.float32)
+    jobs = [(name, gd, k0, min(slab, gd["nz"] - k0)) for k0 in range(0, gd["nz"], slab)]
+    with ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn")) as ex:
+        for k0, arr in ex.map(_phantom_slab, jobs):
+            out[k0:k0 + arr.shape[0]] = arr
+    return out
+
+
+def precision_report(plan, b, xt, torch, wl):
+    """c3: LSQR (lambda 10) and hybrid LSQR (lambda 10), 50 iterations, with
+    the vectors stored in FP32, BF16 and FP16; each result against the FP32
+    path and the phantom."""
+    spec = {"lsqr": dict(lam=10.0), "hybrid_lsqr": dict(lam=10.0)}
+    out = {}
+    for solver, kw in spec.items():
+        ref = None
+        for name in ("f32", "bf16", "f16"):
+            vdt = getattr(torch, DTYPES[name])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, h = plan.solve(b, solver, 50, kw["lam"], vec_dtype=vdt)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            r = {"solve_s": round(dt, 3), "it_per_s": round(50 / dt, 3),
+                 "rel_err_vs_phantom": round(float(torch.linalg.vector_norm(x - xt) / torch.linalg.vector_norm(xt)), 5)}
+            if ref is None:
+                ref = x.clone()
+            else:
+                r["rel_diff_vs_f32_path"] = float(torch.linalg.vector_norm(x - ref) / torch.linalg.vector_norm(ref))
+            out[f"{solver}_{name}"] = r
+            log(f"[precision] {solver} {name}: {r}")
+            del x, h
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,6 +199,13 @@ def main():
                     help="storage of the projector-facing Krylov vectors")
     ap.add_argument("--serve-requests", type=int, default=16)
     ap.add_argument("--serve-scale", type=float, default=0.25)
+    ap.add_argument("--precision", action="store_true",
+                    help="the 16-bit storage report instead of the step benchmark: LSQR and hybrid LSQR "
+                         "(lambda 10, 50 iterations) with FP32, BF16 and FP16 vectors, each compared with the "
+                         "FP32 path; prints its own JSON line")
+    ap.add_argument("--operators-only", action="store_true",
+                    help="projector timings and a short IRN-TV run only (for the largest workloads); prints its "
+                         "own JSON line")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only run the projectors (and a plain 1 GiB copy for counter calibration) "
                          "a few times, for rocprofv3; prints no JSON line")
@@ -162,6 +221,10 @@ def main():
     import paper_2211_14212_amd as kct
     import synth
 
+    big_phantom = None
+    if args.operators_only and synth.WORKLOADS[args.workload]["phantom"]["kind"] == "porous":
+        log("[bench] phantom in slabs (worker processes, before the GPU is used)")
+        big_phantom = phantom_in_slabs(args.workload, synth.geometry(args.workload))
     kct.require_gpu()
     dev = torch.device("cuda", 0)
     wl = args.workload
@@ -174,7 +237,7 @@ def main():
                  "nnz": None, "hit_rays": None}
 
     log(f"[bench] phantom ({wl})")
-    x_true = synth.phantom(wl)
+    x_true = big_phantom if big_phantom is not None else synth.phantom(wl)
     plan = kct.Plan(kg)
     xt = torch.from_numpy(x_true).to(dev)
     if args.profile_kernels:
@@ -200,6 +263,47 @@ def main():
         b, noise_info = synth.add_noise_torch(plan.forward(xt), synth.WORKLOADS[wl]["noise"],
                                               synth.WORKLOADS[wl]["seed"])
     torch.cuda.synchronize()
+
+    if args.precision:
+        rep = precision_report(plan, b, xt, torch, wl)
+        print(json.dumps({"report": "16-bit vector storage vs the FP32 path", "workload": wl, "data": "synthetic",
+                          "results": rep}), flush=True)
+        return
+    if args.operators_only:
+        # Projector timings in the workload's solver storage, one short IRN-TV
+        # run, and the full IRN-TV time extrapolated from its per-iteration cost.
+        # Cached blocks are returned between phases: at 1500^3 the phases
+        # together would not fit the HBM.
+        torch.cuda.empty_cache()
+        sol = synth.WORKLOADS[wl]["solve"]
+        x_in, b_in = xt.to(vdt), b.to(vdt)
+        y_out = torch.empty(kg.proj_shape, device=dev, dtype=vdt)
+        x_out = torch.empty(kg.vol_shape, device=dev, dtype=vdt)
+        fwd_ms = timed(lambda: plan.forward(x_in, out=y_out), args.reps, torch)
+        bwd_ms = timed(lambda: plan.backproject(b_in, out=x_out), args.reps, torch)
+        del x_in, b_in, y_out, x_out
+        torch.cuda.empty_cache()
+        log(f"[bench] fwd {fwd_ms:.1f} ms  bwd {bwd_ms:.1f} ms")
+        rep = {"fwd_ms": round(fwd_ms, 2), "bwd_ms": round(bwd_ms, 2),
+               "fwd_grays_per_s": round(kg.n_rays / (fwd_ms / 1000.0) / 1e9, 3),
+               "bwd_gvoxel_views_per_s": round(kg.n_voxels * len(kg.angles) / (bwd_ms / 1000.0) / 1e9, 3)}
+        if stats.get("nnz"):
+            rep["gsegments_per_s"] = round(stats["nnz"] / (fwd_ms / 1000.0) / 1e9, 2)
+        if "n_outer" in sol:
+            inner = 2
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, h = plan.solve(b, "irn_tv_cgls", 0, sol["lam"], vec_dtype=vdt, tv_outer=1, tv_inner=inner,
+                              tv_eps=sol["eps"])
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            rep["irn_tv_1x2_s"] = round(dt, 3)
+            rep["irn_tv_full_extrapolated_s"] = round(dt / inner * sol["n_outer"] * sol["n_inner"], 1)
+            rep["irn_tv_full"] = f"{sol['n_outer']} outer x {sol['n_inner']} inner, lambda {sol['lam']}"
+            del x, h
+        print(json.dumps({"report": "operators", "workload": wl, "vec_storage": args.vec_dtype, "data": "synthetic",
+                          "results": rep}), flush=True)
+        return
 
     # ---- the step: one CGLS iteration ------------------------------------
     log("[bench] CGLS iterations")

@@ -23,6 +23,9 @@ works it cites for each method).  Equations are named by their labels:
                  GCV or the discrepancy principle (Sec. 2.2.2).
   * AB-/BA-GMRES -- Sec. 2.1.4: GMRES on A B (B a right preconditioner) or
                  on B A (left), for a back projector B that need not be A^T.
+  * SIRT, OS-SART -- the algebraic methods of the comparisons (Sec. 3): the
+                 simultaneous update with inverse row and column sums, and its
+                 ordered-subset form.
   * IRN-TV    -- Sec. 2.3, eqs. (TV), (TV_reweighted), (TV_approx) and
                  Sec. 2.3.1: reweighted quadratic majorants of isotropic TV, each
                  solved by CGLS on [A; lam L D].
@@ -418,6 +421,58 @@ def ba_gmres(A, B, b, n_iter):
     r0 = B(np.asarray(b, dtype=np.float64))
     V, y, hist = _gmres_run(lambda z: B(A(z)), r0, n_iter)
     x = sum(yi * V[i] for i, yi in enumerate(y)) if len(y) else np.zeros_like(r0)
+    return x, hist
+
+
+# --------------------------------------------------------------------------
+# SIRT and OS-SART, the algebraic baselines the paper compares with (Sec. 3).
+# --------------------------------------------------------------------------
+def _inv_or_zero(v):
+    v = np.asarray(v, dtype=np.float64)
+    out = np.zeros_like(v)
+    nz = v != 0
+    out[nz] = 1.0 / v[nz]
+    return out
+
+
+def sirt(A, AT, b, n_iter, lam=1.0):
+    """SIRT: x_{k+1} = x_k + lam V A^T W (b - A x_k) from x_0 = 0, with
+    W = diag(1 / A 1) (inverse ray lengths) and V = diag(1 / A^T 1) (inverse
+    column sums), 0 where a sum vanishes.  hist 'res' = ||b - A x_k|| before
+    update k+1 (the explicit residual of the iterate the step starts from)."""
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros_like(np.asarray(AT(b), dtype=np.float64))
+    W = _inv_or_zero(A(np.ones_like(x)))
+    V = _inv_or_zero(AT(np.ones_like(b)))
+    hist = {"res": []}
+    for _ in range(n_iter):
+        r = b - A(x)
+        hist["res"].append(_nrm(r))
+        x = x + lam * V * AT(W * r)
+    hist["res"] = np.asarray(hist["res"])
+    return x, hist
+
+
+def os_sart(subsets, b_subsets, n_iter, lam=1.0):
+    """OS-SART: one iteration sweeps the ordered subsets s = 1..m of the
+    projection data, x <- x + lam V_s A_s^T W_s (b_s - A_s x) with the SIRT
+    weights of each subset's operator (A_s, A_s^T) = subsets[s].  x_0 = 0.
+    hist 'res' = sqrt(sum_s ||b_s - A_s x||^2), each term taken just before
+    subset s updates x (no extra projection)."""
+    bs = [np.asarray(bb, dtype=np.float64) for bb in b_subsets]
+    A0, AT0 = subsets[0]
+    x = np.zeros_like(np.asarray(AT0(bs[0]), dtype=np.float64))
+    Ws = [_inv_or_zero(A(np.ones_like(x))) for A, _ in subsets]
+    Vs = [_inv_or_zero(AT(np.ones_like(bb))) for (_, AT), bb in zip(subsets, bs)]
+    hist = {"res": []}
+    for _ in range(n_iter):
+        r2 = 0.0
+        for (A, AT), bb, W, V in zip(subsets, bs, Ws, Vs):
+            r = bb - A(x)
+            r2 += _nrm(r) ** 2
+            x = x + lam * V * AT(W * r)
+        hist["res"].append(float(np.sqrt(r2)))
+    hist["res"] = np.asarray(hist["res"])
     return x, hist
 
 

@@ -165,6 +165,11 @@ kct_status kct_plan_create(const kct_geometry *geom, int device, kct_plan **out)
     // Tuning override: KCT_FWD_PREFETCH=0 selects the forward loop without
     // the one-step-ahead gather.
     if (const char *e = std::getenv("KCT_FWD_PREFETCH")) p->fwd_prefetch = std::atoi(e) != 0;
+    // Tuning override: the forward wave's patch width in detector columns.
+    if (const char *e = std::getenv("KCT_FWD_LANES_U")) {
+        const int lu = std::atoi(e);
+        if (lu == 16 || lu == 32 || lu == 64) p->fwd_lane_u = lu;
+    }
     DeviceGuard dg(device);
     if (!dg.ok) {
         delete p;

@@ -105,6 +105,7 @@ struct Plan {
     // Back projector launch shape (chosen from the geometry at plan creation).
     int bwd_kz = 8, bwd_ncmax = 5, bwd_pw = 0, bwd_ph = 0, bwd_fp_angles = 0;
     bool fwd_prefetch = true;     // forward projector gathers one segment ahead
+    int fwd_lane_u = 16;          // forward wave patch: lane_u x (64 / lane_u) rays (64, 32 or 16)
     bool bwd_acc_lds = true;      // back projector keeps per-voxel sums in LDS
     size_t bwd_lds = 0;
     int64_t n_vox() const { return int64_t(gp.nx) * gp.ny * gp.nz; }

@@ -94,7 +94,7 @@ __global__ __launch_bounds__(256) void k_backward(const TP *__restrict__ proj, T
     double *rinv = cinv + 2 * pw_max;                         // ph_max
     int4 *fps = reinterpret_cast<int4 *>(rinv + ph_max);      // fp_angles tile footprints
     float *accs = reinterpret_cast<float *>(fps + fp_angles);  // KZ * 256 when ACC_LDS
-    double *patch = reinterpret_cast<double *>(accs + (ACC_LDS ? KZ * 256 : 0)); // pw_max * ph_max + NCM
+    float *patch = accs + (ACC_LDS ? KZ * 256 : 0);            // pw_max * ph_max + NCM
     __shared__ double red[4];
 
     const int64_t g8 = (groups + 7) / 8;
@@ -170,7 +170,7 @@ __global__ __launch_bounds__(256) void k_backward(const TP *__restrict__ proj, T
             const int iu = iu_lo + c, iv = iv_lo + r;
             const float uu = float((iu - g.cu) * g.du), vv = float((iv - g.cv) * g.dv);
             const float yv = to_f32(ya[int64_t(iv) * g.nu + iu]);
-            patch[e] = double(yv * sqrtf(dsd * dsd + uu * uu + vv * vv));
+            patch[e] = yv * sqrtf(dsd * dsd + uu * uu + vv * vv);
         }
         for (int c = threadIdx.x; c < pw; c += 256) {
             // 1/d per axis; 0 marks a ray parallel to that axis's planes.
@@ -182,7 +182,7 @@ __global__ __launch_bounds__(256) void k_backward(const TP *__restrict__ proj, T
         for (int r = threadIdx.x; r < ph; r += 256) rinv[r] = invv[iv_lo + r];
         // The unrolled column loop reads up to NCM-1 values past the patch;
         // they are multiplied by a zero length, so they must be finite.
-        if (threadIdx.x < NCM) patch[pw * ph + threadIdx.x] = 0.0;
+        if (threadIdx.x < NCM) patch[pw * ph + threadIdx.x] = 0.f;
         __syncthreads();
 
         if (valid) {
@@ -245,7 +245,7 @@ __global__ __launch_bounds__(256) void k_backward(const TP *__restrict__ proj, T
                     hi[c] = fmin(xh, yh);
                 }
             }
-            const double *pcol = patch + (c_lo - iu_lo);
+            const float *pcol = patch + (c_lo - iu_lo);
             const float rmin = dsd * fast_rcp(cwmin), rmax = dsd * fast_rcp(cwmax);
             const int r_end = iv_lo + ph - 1;
             // The z run, compiled for the wave's column count NC <= NCM.  Row
@@ -265,10 +265,7 @@ __global__ __launch_bounds__(256) void k_backward(const TP *__restrict__ proj, T
                         const double z0 = g.Z0 + k * g.vz, z1 = z0 + g.vz;
                         const int r_lo = max(iv_lo, int(ceilf(vlo_b * idv + cv - margin)));
                         const int r_hi = min(r_end, int(floorf(vhi_t * idv + cv + margin)));
-                        // This angle's sum for the voxel in FP64 (the staged values
-                        // are FP64 too, so a candidate costs min, max, a clamped
-                        // subtraction and one FMA); one rounding into the FP32 sum.
-                        double sv = 0.0;
+                        float s = ACC_LDS ? accs[kk * 256 + threadIdx.x] : acc[ACC_LDS ? 0 : kk];
                         for (int r = r_lo; r <= r_hi; ++r) {
                             // 1/v of the row (a huge positive value for v = 0, which
                             // keeps the half-open rule: z0 <= 0 < z1 gives an
@@ -276,18 +273,18 @@ __global__ __launch_bounds__(256) void k_backward(const TP *__restrict__ proj, T
                             const double iv = rinv[r - iv_lo];
                             const double ta = z0 * iv, tb = z1 * iv;
                             const double zl = fmin(ta, tb), zh = fmax(ta, tb);
-                            const double *prow = pcol + (r - iv_lo) * pw;
+                            const float *prow = pcol + (r - iv_lo) * pw;
 #pragma unroll
                             for (int c = 0; c < NC; ++c) {
                                 const double len = fmin(hi[c], zh) - fmax(lo[c], zl);
                                 // Clamping to [0, 1] (an interval inside one voxel
                                 // is far shorter than the whole ray) folds into
                                 // the subtraction's clamp bit.
-                                sv = fma(fmin(fmax(len, 0.0), 1.0), prow[c], sv);
+                                s = fmaf(float(fmin(fmax(len, 0.0), 1.0)), prow[c], s);
                             }
                         }
-                        if constexpr (ACC_LDS) accs[kk * 256 + threadIdx.x] += float(sv);
-                        else acc[ACC_LDS ? 0 : kk] += float(sv);
+                        if constexpr (ACC_LDS) accs[kk * 256 + threadIdx.x] = s;
+                        else acc[ACC_LDS ? 0 : kk] = s;
                     }
                     vlo_b = vlo_t;
                 }
@@ -295,6 +292,7 @@ __global__ __launch_bounds__(256) void k_backward(const TP *__restrict__ proj, T
             if (NCM >= 2 && ncw <= 2) zrun(std::integral_constant<int, (NCM >= 2 ? 2 : NCM)>{});
             else if (NCM >= 3 && ncw <= 3) zrun(std::integral_constant<int, (NCM >= 3 ? 3 : NCM)>{});
             else if (NCM >= 4 && ncw <= 4) zrun(std::integral_constant<int, (NCM >= 4 ? 4 : NCM)>{});
+            else if (NCM >= 8 && ncw <= 8) zrun(std::integral_constant<int, (NCM >= 8 ? 8 : NCM)>{});
             else zrun(std::integral_constant<int, NCM>{});
         }
     }
@@ -367,6 +365,7 @@ kct_status bwd_launch2(Plan &p, const void *proj, void *vol, const Epilogue &ep,
     case 3: return bwd_launch3<TP, TV, KZ, 3>(p, proj, vol, ep, st);
     case 4: return bwd_launch3<TP, TV, KZ, 4>(p, proj, vol, ep, st);
     case 8: return bwd_launch3<TP, TV, KZ, 8>(p, proj, vol, ep, st);
+    case 16: return bwd_launch3<TP, TV, KZ, 16>(p, proj, vol, ep, st);
     }
     return fail(KCT_E_GEOMETRY, "unsupported back projector footprint width");
 }
@@ -401,9 +400,9 @@ kct_status choose_bwd_shape(Plan &p)
     const double vox_diag = std::sqrt(g.vx * g.vx + g.vy * g.vy);
     const double ncols = std::floor(vox_diag * mag / g.du + 0.02) + 1.0;
     int ncm = 0;
-    for (int c : {2, 3, 4, 8})
+    for (int c : {2, 3, 4, 8, 16})
         if (ncols <= c) { ncm = c; break; }
-    if (!ncm) return fail(KCT_E_GEOMETRY, "voxels project onto more than 8 detector columns");
+    if (!ncm) return fail(KCT_E_GEOMETRY, "voxels project onto more than 16 detector columns");
     p.bwd_ncmax = ncm;
 
     // The deepest z run per thread (16, else 8 voxels) that still leaves
@@ -436,7 +435,7 @@ kct_status choose_bwd_shape(Plan &p)
         p.bwd_pw = int(std::min<double>(pw, g.nu));
         p.bwd_ph = int(std::min<double>(ph, g.nv));
         p.bwd_lds = size_t(p.bwd_pw) * 16 + size_t(p.bwd_ph) * 8 + size_t(p.bwd_fp_angles) * 16 +
-                    (size_t(p.bwd_pw) * p.bwd_ph + 8) * sizeof(double);
+                    (size_t(p.bwd_pw) * p.bwd_ph + 8) * sizeof(float);
         if (p.bwd_lds + size_t(p.bwd_kz) * 256 * sizeof(float) <= 64 * 1024) return KCT_OK;
         if (p.bwd_fp_angles > 0) {
             p.bwd_fp_angles = 0;

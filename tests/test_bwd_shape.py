@@ -47,11 +47,17 @@ def _footprints(gd, x0, x1, y0, y1, z0, z1, angles):
 
 
 @pytest.mark.parametrize("name,crop", [("cgls32", None), ("medical256", None), ("torso512", None),
-                                       ("muct1500", None), ("serve_big", None)])
+                                       ("muct1500", None), ("serve_big", None), ("serve_fine", None)])
 def test_launch_bounds_are_conservative(name, crop):
     if name == "serve_big":
         gd = synth.geometry(dict(nx=512, ny=512, nz=512, vx=0.5, vy=0.5, vz=0.5, nu=256, nv=256,
                                  du=1.1 * 512 * 0.5 * 1.5 / 256, dv=1.1 * 512 * 0.5 * 1.5 / 256, dso=1000.0,
+                                 dsd=1500.0, n_angles=90))
+    elif name == "serve_fine":
+        # The request stream's finest case: 128^3 on a 1024^2 detector, about
+        # 7 pixels per voxel width.
+        gd = synth.geometry(dict(nx=128, ny=128, nz=128, vx=0.5, vy=0.5, vz=0.5, nu=1024, nv=1024,
+                                 du=1.1 * 128 * 0.5 * 1.5 / 1024, dv=1.1 * 128 * 0.5 * 1.5 / 1024, dso=1000.0,
                                  dsd=1500.0, n_angles=90))
     else:
         gd = synth.geometry(name)

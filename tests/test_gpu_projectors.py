@@ -39,6 +39,10 @@ def _geoms():
         "muct_crop": synth.crop_geometry("muct1500", 64, 48, 32),
         "torso_crop": synth.geometry(dict(nx=48, ny=48, nz=40, vx=0.5, vy=0.5, vz=0.5, nu=96, nv=72, du=0.4,
                                           dv=0.4, dso=1000.0, dsd=1500.0, n_angles=30)),
+        # A detector much finer than the voxels' images (about 10 columns per
+        # voxel diagonal), as in the request stream's small-volume cases.
+        "fine_detector": synth.geometry(dict(nx=20, ny=20, nz=18, vx=0.5, vy=0.5, vz=0.5, nu=160, nv=150, du=0.1,
+                                             dv=0.1, dso=1000.0, dsd=1500.0, n_angles=12)),
     }
 
 

@@ -310,3 +310,38 @@ def test_gmres_krylov_optimality_unmatched(k):
     Q, _ = np.linalg.qr(np.array(K).T)
     y, *_ = np.linalg.lstsq(Bm @ A @ Q, Bm @ b, rcond=None)
     assert np.linalg.norm(xb - Q @ y) <= 1e-8 * np.linalg.norm(Q @ y)
+
+
+# ---- SIRT and OS-SART (the comparison methods of Sec. 3) --------------------
+
+def _positive_problem(m=40, n=12, seed=11):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(0.1, 1.0, (m, n)), rng
+
+
+def test_sirt_fixed_point_is_weighted_least_squares():
+    """SIRT's fixed point solves A^T W (b - A x) = 0: the least-squares
+    solution in the W-weighted norm, here found by lstsq on W^(1/2) A."""
+    A, rng = _positive_problem()
+    b = rng.uniform(0.5, 2.0, A.shape[0])
+    x, h = S.sirt(*_ops(A), b, 4000)
+    w = 1.0 / A.sum(1)
+    ref, *_ = np.linalg.lstsq(np.sqrt(w)[:, None] * A, np.sqrt(w) * b, rcond=None)
+    assert np.linalg.norm(x - ref) <= 1e-8 * np.linalg.norm(ref)
+
+
+def test_os_sart_one_subset_is_sirt_and_solves_consistent_systems():
+    A, rng = _positive_problem(seed=12)
+    xt = rng.uniform(0.0, 1.0, A.shape[1])
+    b = A @ xt
+    Af, ATf = _ops(A)
+    x1, h1 = S.os_sart([(Af, ATf)], [b], 30)
+    xs, hs = S.sirt(Af, ATf, b, 30)
+    assert np.linalg.norm(x1 - xs) <= 1e-12 * np.linalg.norm(xs)
+    np.testing.assert_allclose(h1["res"], hs["res"], rtol=1e-12)
+    # Four interleaved subsets of the rows: the consistent system's solution.
+    parts = [np.arange(s, A.shape[0], 4) for s in range(4)]
+    subs = [((lambda x, P=P: A[P] @ x), (lambda y, P=P: A[P].T @ y)) for P in parts]
+    x4, h4 = S.os_sart(subs, [b[P] for P in parts], 3000)
+    assert np.linalg.norm(x4 - xt) <= 1e-6 * np.linalg.norm(xt)
+    assert h4["res"][-1] < 1e-6 * h4["res"][0]
