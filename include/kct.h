@@ -147,8 +147,12 @@ typedef enum kct_solver {
     KCT_AB_GMRES = 5,    /* Sec. 2.1.4: GMRES on A B (B = the chosen back projector
                             as right preconditioner); stores k+1 projection-space
                             basis vectors                                          */
-    KCT_BA_GMRES = 6     /* Sec. 2.1.4: GMRES on B A (left preconditioner); stores
+    KCT_BA_GMRES = 6,    /* Sec. 2.1.4: GMRES on B A (left preconditioner); stores
                             k+1 volume-space basis vectors                         */
+    KCT_SIRT = 7,        /* Sec. 3's algebraic baseline: x += lam V A^T W (b - A x),
+                            W = 1 / (A 1), V = 1 / (A^T 1); lambda in (0, 2)       */
+    KCT_OS_SART = 8      /* SIRT's update over n_subsets ordered angle subsets per
+                            iteration (subset s: angles a with a mod n_subsets = s) */
 } kct_solver;
 
 /* The back projector B of AB-/BA-GMRES.  Every other solver uses A^T. */
@@ -177,11 +181,14 @@ typedef enum kct_lambda_rule {
  * inner iteration).
  *   [0] residual norm the method recurs: CGLS ||b - A x_k||, LSQR and hybrid
  *       ||[b;0] - [A; lam I] x_k||, LSMR ||[A; lam I]^T r_k||, IRN-TV ||b - A x||,
- *       AB-GMRES ||b - A x_k||, BA-GMRES ||B (b - A x_k)||;
+ *       AB-GMRES ||b - A x_k||, BA-GMRES ||B (b - A x_k)||, SIRT ||b - A x_k||
+ *       before update k+1, OS-SART sqrt(sum_s ||b_s - A_s x||^2) with each
+ *       term taken just before subset s updates x;
  *   [1] alpha_k; [2] beta_k (the method's own two leading scalars; GMRES:
  *       H[k+1, k] and the k-th diagonal entry of the rotated Hessenberg matrix);
  *   [3] 1 if the method had broken down (zero norm) by this iteration, 2 if a
- *       scalar became non-finite, else 0;
+ *       scalar became non-finite, 3 if the explicit residual rule stopped it,
+ *       else 0;
  *   [4] lambda_k, the Tikhonov parameter of iteration k (the fixed lambda, or
  *       hybrid LSQR's GCV / DP choice; IRN-TV: the TV weight lambda). */
 #define KCT_HIST_COLS 5
@@ -198,8 +205,17 @@ typedef struct kct_solve_params {
     int32_t lambda_rule; /* kct_lambda_rule; not FIXED only for hybrid LSQR      */
     double noise_level;  /* DP: relative noise level ||e|| / ||b||, in (0, inf)  */
     int32_t backprojector; /* kct_backprojector; not MATCHED only for the GMRES  */
-    int32_t reserved;    /* 0                                                    */
+    int32_t n_subsets;   /* OS-SART: ordered subsets (1..n_angles); else 0      */
+    uint32_t flags;      /* KCT_FLAG_* bits; unknown bits are KCT_E_INVALID_ARG  */
+    int32_t reserved;    /* must be 0                                            */
 } kct_solve_params;
+
+/* Stop when the explicit residual ||b - A x_k|| grows (CGLS, LSQR, LSMR;
+ * Sec. 3.1.1: the toolbox's guard against lost orthogonality and accumulated
+ * rounding).  Costs one more forward projection per iteration.  When it
+ * triggers, x is the iterate before the increase, history column 3 holds 3
+ * from that row on, and column 0 holds the explicit residual throughout. */
+#define KCT_FLAG_STOP_ON_RESIDUAL_INCREASE 1u
 
 /* Workspace bytes kct_solve needs for `params` on `plan`. */
 kct_status kct_solve_workspace_bytes(const kct_plan *plan, const kct_solve_params *params,

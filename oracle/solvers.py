@@ -26,6 +26,8 @@ works it cites for each method).  Equations are named by their labels:
   * SIRT, OS-SART -- the algebraic methods of the comparisons (Sec. 3): the
                  simultaneous update with inverse row and column sums, and its
                  ordered-subset form.
+  * stop rule -- Sec. 3.1.1 and 3.1.2: stop when the residual computed
+                 from the iterate grows between two iterations.
   * IRN-TV    -- Sec. 2.3, eqs. (TV), (TV_reweighted), (TV_approx) and
                  Sec. 2.3.1: reweighted quadratic majorants of isotropic TV, each
                  solved by CGLS on [A; lam L D].
@@ -426,6 +428,31 @@ def ba_gmres(A, B, b, n_iter):
 
 # --------------------------------------------------------------------------
 # SIRT and OS-SART, the algebraic baselines the paper compares with (Sec. 3).
+
+# ---------------------------------------------------------------------------
+# Explicit-residual stop rule (Sec. 3.1.1 and 3.1.2): after each iteration the
+# residual ||b - A x_k|| is computed from the iterate itself, not recurred; the
+# first time it is larger than at the previous iteration the run stops and
+# returns the previous iterate.  Reading: the comparison starts with the pair
+# (x_1, x_2); x_0 = 0 is not compared.
+
+
+def explicit_residual_stop(A, b, iterates):
+    """Apply the rule to the iterates x_1..x_n.
+
+    Returns (k, x, res): k is the 0-based index of the first iterate whose
+    explicit residual exceeds its predecessor's (None if none does), x the
+    iterate returned (x_{k-1} in that 0-based numbering, else the last one) and
+    res the explicit residual norms up to and including iterate k.
+    """
+    res = []
+    for k, x in enumerate(iterates):
+        res.append(_nrm(b - A(x)))
+        if k > 0 and res[k] > res[k - 1]:
+            return k, iterates[k - 1], np.asarray(res)
+    return None, iterates[-1], np.asarray(res)
+
+
 # --------------------------------------------------------------------------
 def _inv_or_zero(v):
     v = np.asarray(v, dtype=np.float64)

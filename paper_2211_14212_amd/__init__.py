@@ -24,7 +24,8 @@ from ._lib import (KCT_BF16, KCT_CGLS, KCT_F16, KCT_F32, KCT_HIST_COLS, KCT_HYBR
 __all__ = ["Geometry", "Plan", "State", "SOLVERS", "require_gpu", "KctError", "dtype_code", "library_path"]
 
 SOLVERS = {"cgls": KCT_CGLS, "lsqr": KCT_LSQR, "lsmr": KCT_LSMR, "hybrid_lsqr": KCT_HYBRID_LSQR,
-           "irn_tv_cgls": KCT_IRN_TV_CGLS, "ab_gmres": _lib.KCT_AB_GMRES, "ba_gmres": _lib.KCT_BA_GMRES}
+           "irn_tv_cgls": KCT_IRN_TV_CGLS, "ab_gmres": _lib.KCT_AB_GMRES, "ba_gmres": _lib.KCT_BA_GMRES,
+           "sirt": _lib.KCT_SIRT, "os_sart": _lib.KCT_OS_SART}
 _DT = {torch.float32: KCT_F32, torch.bfloat16: KCT_BF16, torch.float16: KCT_F16}
 
 
@@ -102,12 +103,13 @@ BACKPROJECTORS = {"matched": _lib.KCT_BP_MATCHED, "interp": _lib.KCT_BP_INTERP}
 
 
 def _params(solver, n_iter, lam, vec_dtype, tv_outer=0, tv_inner=0, tv_eps=1e-3, lam_rule="fixed",
-            noise_level=0.0, backprojector="matched"):
+            noise_level=0.0, backprojector="matched", n_subsets=0, stop_on_residual_increase=False):
     code = SOLVERS[solver] if isinstance(solver, str) else int(solver)
     rule = LAMBDA_RULES[lam_rule] if isinstance(lam_rule, str) else int(lam_rule)
     bp = BACKPROJECTORS[backprojector] if isinstance(backprojector, str) else int(backprojector)
     return _lib.KctSolveParams(code, int(n_iter), float(lam), int(tv_outer), int(tv_inner), float(tv_eps),
-                               dtype_code(vec_dtype), rule, float(noise_level), bp, 0)
+                               dtype_code(vec_dtype), rule, float(noise_level), bp, int(n_subsets),
+                               _lib.KCT_FLAG_STOP_ON_RESIDUAL_INCREASE if stop_on_residual_increase else 0, 0)
 
 
 class Plan:
@@ -210,7 +212,9 @@ class Plan:
 
         Keyword options: tv_outer, tv_inner, tv_eps (IRN-TV); lam_rule
         ("fixed", "gcv" or "dp") and noise_level (hybrid LSQR); backprojector
-        ("matched" or "interp", AB-/BA-GMRES).  history is an
+        ("matched" or "interp", AB-/BA-GMRES); n_subsets (OS-SART; lam is
+        the relaxation of SIRT and OS-SART); stop_on_residual_increase
+        (CGLS, LSQR, LSMR).  history is an
         (n_rows, KCT_HIST_COLS) float64 device tensor or None.  The call only
         enqueues work on the stream.
         """

@@ -19,9 +19,12 @@ STATUS_NAMES = {0: "KCT_OK", 1: "KCT_E_INVALID_ARG", 2: "KCT_E_GEOMETRY", 3: "KC
 # kct_dtype
 KCT_F32, KCT_BF16, KCT_F16 = 0, 1, 2
 # kct_solver
-KCT_CGLS, KCT_LSQR, KCT_LSMR, KCT_HYBRID_LSQR, KCT_IRN_TV_CGLS, KCT_AB_GMRES, KCT_BA_GMRES = 0, 1, 2, 3, 4, 5, 6
+(KCT_CGLS, KCT_LSQR, KCT_LSMR, KCT_HYBRID_LSQR, KCT_IRN_TV_CGLS, KCT_AB_GMRES, KCT_BA_GMRES, KCT_SIRT,
+ KCT_OS_SART) = range(9)
 # kct_backprojector
 KCT_BP_MATCHED, KCT_BP_INTERP = 0, 1
+# flags
+KCT_FLAG_STOP_ON_RESIDUAL_INCREASE = 1
 KCT_HIST_COLS = 5
 # kct_lambda_rule
 KCT_LAMBDA_FIXED, KCT_LAMBDA_GCV, KCT_LAMBDA_DP = 0, 1, 2
@@ -52,7 +55,8 @@ class KctSolveParams(ctypes.Structure):
         ("solver", ctypes.c_int32), ("n_iter", ctypes.c_int32), ("lam", ctypes.c_double),
         ("tv_outer", ctypes.c_int32), ("tv_inner", ctypes.c_int32), ("tv_eps", ctypes.c_double),
         ("vec_dtype", ctypes.c_int32), ("lambda_rule", ctypes.c_int32), ("noise_level", ctypes.c_double),
-        ("backprojector", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("backprojector", ctypes.c_int32), ("n_subsets", ctypes.c_int32),
+        ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32),
     ]
 
 

@@ -13,6 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkct.so")
 SOURCES = ["api.hip", "proj_fwd.hip", "proj_bwd.hip", "proj_interp.hip", "krylov_kernels.hip", "tv_kernels.hip", "gmres.hip",
+           "sart.hip",
            "solve.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -82,6 +82,7 @@ enum ScalarIdx : int {
     S_LAMBDA, S_PNORM2, S_LAST,
     S_DONE, S_ITER, S_HROW, S_KGK, S_RES,
     S_HLAM,                        // lambda reported in history column 4
+    S_PREV_EXPL,                   // last explicit residual (stop rule; < 0 before the first)
     // Coefficients the scalar kernels leave for the next vector kernels:
     S_F0 = 24, S_F1,               // forward projector epilogue (2)
     S_B0, S_B1, S_B2, S_B3,        // back projector epilogue (4)

@@ -189,6 +189,7 @@ __global__ __launch_bounds__(256) void k_sc_cgls_init(double *S, const double *p
     if (threadIdx.x != 0) return;
     S[S_LAMBDA] = lam;
     S[S_HLAM] = lam;
+    S[S_PREV_EXPL] = -1.0;
     S[S_GAMMA] = g;
     S[S_PNORM2] = g;
     S[S_ITER] = n_iter;
@@ -252,6 +253,7 @@ __global__ __launch_bounds__(256) void k_sc_gk_init1(double *S, const double *pu
     const double beta = sqrt(b2);
     S[S_LAMBDA] = lam;
     S[S_HLAM] = lam;
+    S[S_PREV_EXPL] = -1.0;
     S[S_ITER] = n_iter;
     S[S_HROW] = 0.0;
     S[S_KGK] = 0.0;
@@ -457,6 +459,45 @@ __global__ __launch_bounds__(64) void k_hybrid_solve(double *S, const double *gk
         coef[c] = M[c * m + c] != 0.0 ? v / M[c * m + c] : 0.0;
     }
     for (int c = 0; c < k; ++c) coef[c] /= gk[2 * c + 1];
+}
+
+// ---------------------------------------------------------------------------
+// Explicit-residual stop rule: x_prev = x before each iteration while the run
+// is live; after it, ||b - A x_k|| from the forward projector's partial sums;
+// when it exceeds the previous one the run is done (3) and x is put back to
+// x_prev on this and every later iteration (idempotent: x_prev no longer moves).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_save_x(const float *__restrict__ x, float *__restrict__ xp, int64_t n,
+                                                const double *__restrict__ S)
+{
+    if (S[S_DONE] != 0.0) return;
+    for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < n; e += int64_t(gridDim.x) * 256) xp[e] = x[e];
+}
+
+__global__ __launch_bounds__(256) void k_restore_x(float *__restrict__ x, const float *__restrict__ xp, int64_t n,
+                                                   const double *__restrict__ S)
+{
+    if (S[S_DONE] != 3.0) return;
+    for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < n; e += int64_t(gridDim.x) * 256) x[e] = xp[e];
+}
+
+__global__ __launch_bounds__(256) void k_sc_explicit(double *S, const double *p, int64_t n, double *hist)
+{
+    const double r2 = reduce_parts(p, n);
+    if (threadIdx.x != 0) return;
+    const double r = sqrt(r2);
+    if (S[S_DONE] == 0.0) {
+        if (!finite(r)) S[S_DONE] = 2.0;
+        else if (S[S_PREV_EXPL] >= 0.0 && r > S[S_PREV_EXPL]) S[S_DONE] = 3.0;
+        else S[S_PREV_EXPL] = r;
+    }
+    if (hist) {
+        const int64_t row = int64_t(S[S_HROW]) - 1;
+        if (row >= 0 && row < int64_t(S[S_ITER])) {
+            hist[row * KCT_HIST_COLS + 0] = r;
+            hist[row * KCT_HIST_COLS + 3] = S[S_DONE];
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -862,6 +903,21 @@ kct_status sk_hybrid_solve(double *S, const double *gk, double *work, double *co
 {
     SC1(k_hybrid_solve, dim3(1), dim3(64), 0, st, S, gk, work, coef);
     return check_hip(hipGetLastError(), "hybrid projected solve");
+}
+kct_status vk_save_x(const float *x, float *xp, int64_t n, const double *S, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_save_x, dim3(vec_groups(n)), dim3(256), 0, st, x, xp, n, S);
+    return check_hip(hipGetLastError(), "save x");
+}
+kct_status vk_restore_x(float *x, const float *xp, int64_t n, const double *S, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_restore_x, dim3(vec_groups(n)), dim3(256), 0, st, x, xp, n, S);
+    return check_hip(hipGetLastError(), "restore x");
+}
+kct_status sk_explicit(double *S, Reduced r, double *hist, hipStream_t st)
+{
+    SC1(k_sc_explicit, dim3(1), dim3(256), 0, st, S, r.ptr, r.n, hist);
+    return check_hip(hipGetLastError(), "explicit residual");
 }
 kct_status sk_hybrid_choose(double *S, const double *gk, double *work, double *coef, double *hist, int rule,
                             double noise_level, hipStream_t st)

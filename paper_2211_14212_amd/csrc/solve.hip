@@ -23,12 +23,18 @@
 //           Givens update of H and of the residual.  At the end
 //           x = B (sum_i y_i V_i).  BA-GMRES: t = A V_j; V_{j+1} = B t; ...;
 //           x = sum_i y_i V_i.
+//   SIRT / OS-SART (Sec. 3) per subset s: r_s = b_s - A_s x -> ||r_s||^2;
+//           r_s *= W; v = A_s^T r_s; x += lam V_s v.  The angles are
+//           permuted once so that every subset is a contiguous block, and the
+//           projectors run on a view of the plan holding that block.
 
 #include "gmres.hpp"
 #include "krylov.hpp"
+#include "sart.hpp"
 
 #include <cmath>
 #include <new>
+#include <vector>
 
 namespace kct {
 
@@ -45,7 +51,9 @@ struct Layout {
     int64_t nparts = 0;
 };
 
-bool solver_ok(int s) { return s >= KCT_CGLS && s <= KCT_BA_GMRES; }
+bool solver_ok(int s) { return s >= KCT_CGLS && s <= KCT_OS_SART; }
+
+bool is_sart(int s) { return s == KCT_SIRT || s == KCT_OS_SART; }
 
 bool is_gmres(int s) { return s == KCT_AB_GMRES || s == KCT_BA_GMRES; }
 
@@ -66,6 +74,22 @@ kct_status check_params(const kct_solve_params *prm)
         if (!is_gmres(prm->solver))
             return fail(KCT_E_INVALID_ARG, "only AB- and BA-GMRES take an unmatched back projector");
     }
+    if (prm->flags & ~KCT_FLAG_STOP_ON_RESIDUAL_INCREASE) return fail(KCT_E_INVALID_ARG, "unknown flags");
+    if (prm->reserved != 0) return fail(KCT_E_INVALID_ARG, "reserved must be 0");
+    if ((prm->flags & KCT_FLAG_STOP_ON_RESIDUAL_INCREASE) && prm->solver != KCT_CGLS && prm->solver != KCT_LSQR &&
+        prm->solver != KCT_LSMR)
+        return fail(KCT_E_INVALID_ARG, "the explicit-residual stop rule is for CGLS, LSQR and LSMR");
+    if (is_sart(prm->solver)) {
+        if (!(prm->lambda > 0.0 && prm->lambda < 2.0))
+            return fail(KCT_E_INVALID_ARG, "SIRT / OS-SART need a relaxation lambda in (0, 2)");
+        if (prm->vec_dtype != KCT_F32) return fail(KCT_E_DTYPE, "SIRT / OS-SART run in FP32");
+        if (prm->solver == KCT_OS_SART && prm->n_subsets < 1)
+            return fail(KCT_E_INVALID_ARG, "OS-SART needs n_subsets >= 1");
+        if (prm->solver == KCT_SIRT && prm->n_subsets > 1)
+            return fail(KCT_E_INVALID_ARG, "SIRT takes no subsets (use OS-SART)");
+    } else if (prm->n_subsets != 0) {
+        return fail(KCT_E_INVALID_ARG, "n_subsets is for OS-SART only");
+    }
     if (is_gmres(prm->solver)) {
         if (prm->lambda != 0.0) return fail(KCT_E_INVALID_ARG, "AB-/BA-GMRES solve the undamped problem (lambda 0)");
         // Unit basis vectors have entries near 1/sqrt(n): below FP16's normal range.
@@ -82,6 +106,13 @@ kct_status check_params(const kct_solve_params *prm)
     return KCT_OK;
 }
 
+kct_status check_params_plan(const Plan &p, const kct_solve_params &prm)
+{
+    if (prm.solver == KCT_OS_SART && prm.n_subsets > p.gp.na)
+        return fail(KCT_E_INVALID_ARG, "OS-SART has more subsets than angles");
+    return KCT_OK;
+}
+
 Layout layout(const Plan &p, const kct_solve_params &prm)
 {
     Layout L;
@@ -95,7 +126,9 @@ Layout layout(const Plan &p, const kct_solve_params &prm)
     L.pb = o; o += up(sizeof(double) * L.nparts);
     L.pc = o; o += up(sizeof(double) * L.nparts);
     L.stage = o; o += up(sizeof(double) * 3 * 256);
-    L.pad = o; o += up(size_t(2 * p.pad.vox) * vt);
+    const bool expl = prm.flags & KCT_FLAG_STOP_ON_RESIDUAL_INCREASE;
+    // The stop rule projects x itself (FP32), so its padded copy needs FP32.
+    L.pad = o; o += up(size_t(2 * p.pad.vox) * (expl ? std::max<size_t>(vt, 4) : vt));
     const int k = prm.n_iter;
     switch (prm.solver) {
     case KCT_CGLS:
@@ -135,6 +168,19 @@ Layout layout(const Plan &p, const kct_solve_params &prm)
         L.coef = o; o += up(sizeof(double) * (size_t(k) + 1));
         break;
     }
+    case KCT_SIRT:
+    case KCT_OS_SART: {
+        const int m = prm.solver == KCT_SIRT ? 1 : prm.n_subsets;
+        L.v[0] = o; o += up(size_t(N) * 4);              // residual r (permuted angle order)
+        L.v[1] = o; o += up(size_t(M) * 4);              // A_s^T (W r_s)
+        L.v[2] = o; o += up(size_t(N) * 4);              // W
+        L.v[3] = o; o += up(size_t(M) * 4 * size_t(m));  // V_1..V_m
+        if (m > 1) {
+            L.v[4] = o; o += up(size_t(N) * 4);          // b in the permuted angle order
+            L.work = o; o += up(sizeof(AngleGeo) * size_t(p.gp.na));
+        }
+        break;
+    }
     case KCT_IRN_TV_CGLS:
         L.v[0] = o; o += up(size_t(N) * vt);    // r1
         L.v[1] = o; o += up(size_t(N) * vt);    // q1
@@ -143,6 +189,10 @@ Layout layout(const Plan &p, const kct_solve_params &prm)
         L.v[4] = o; o += up(size_t(M) * 4 * 3); // r2 (gradient space, FP32)
         L.v[5] = o; o += up(size_t(M) * 4);     // L weights
         break;
+    }
+    if (expl) {
+        L.v[4] = o; o += up(size_t(M) * 4); // x of the previous iteration
+        L.v[5] = o; o += up(size_t(N) * 4); // b - A x_k
     }
     L.total = o;
     return L;
@@ -167,6 +217,11 @@ struct kct_state {
     bool started = false;
     bool finalized = false;
     int total = 0; // iterations to run (IRN-TV: outer * inner)
+    // SIRT / OS-SART: the plan restricted to each subset's block of the
+    // permuted angles (views: they share the plan's device buffers), the
+    // first angle of each block (and the angle count at the end).
+    std::vector<kct::Plan> sub;
+    std::vector<int> sub_a0;
 
     double *S() const { return reinterpret_cast<double *>(ws + L.scal); }
     double *pa() const { return reinterpret_cast<double *>(ws + L.pa); }
@@ -476,6 +531,75 @@ kct_status gm_finish(kct_state &s)
     return apply_B(s, z, KCT_F32, s.x, KCT_F32, plain);                 // x = B (...)
 }
 
+// ---------------------------------------------------------------- SIRT / OS-SART
+int sa_m(const kct_state &s) { return s.prm.solver == KCT_SIRT ? 1 : s.prm.n_subsets; }
+float *sa_r(kct_state &s) { return static_cast<float *>(s.v(0)); }
+float *sa_v(kct_state &s) { return static_cast<float *>(s.v(1)); }
+float *sa_W(kct_state &s) { return static_cast<float *>(s.v(2)); }
+float *sa_V(kct_state &s, int k) { return static_cast<float *>(s.v(3)) + size_t(k) * size_t(s.M()); }
+const float *sa_b(kct_state &s) { return sa_m(s) > 1 ? static_cast<const float *>(s.v(4)) : s.b; }
+size_t sa_off(const kct_state &s, int k) { return size_t(s.sub_a0[k]) * size_t(s.plan->gp.nv) * s.plan->gp.nu; }
+
+kct_status sa_init(kct_state &s)
+{
+    Plan &p = *s.plan;
+    const int m = sa_m(s), na = p.gp.na;
+    // Subset k: angles a = k, k + m, ...; laid out as the k-th contiguous block.
+    s.sub_a0.clear();
+    for (int k = 0; k <= m; ++k) s.sub_a0.push_back(k < m ? sa_block_start(k, na, m) : na);
+    AngleGeo *tab = p.d_tab;
+    if (m > 1) {
+        tab = reinterpret_cast<AngleGeo *>(s.ws + s.L.work);
+        KCT_TRY(sa_permute(tab, p.d_tab, static_cast<float *>(s.v(4)), s.b, na, int64_t(p.gp.nv) * p.gp.nu, m, s.st));
+    }
+    s.sub.assign(m, p);
+    for (int k = 0; k < m; ++k) {
+        Plan &v = s.sub[k];
+        v.d_tab = tab + s.sub_a0[k];
+        v.gp.na = s.sub_a0[k + 1] - s.sub_a0[k];
+        v.bwd_fp_angles = std::min(v.bwd_fp_angles, v.gp.na);
+    }
+    Epilogue plain;
+    // W = 1 / (A 1): every block's rays through a volume of ones.
+    KCT_TRY(vk_fill(sa_v(s), KCT_F32, s.M(), 1.f, s.st));
+    KCT_TRY(launch_pad_volume(p, sa_v(s), KCT_F32, s.pad(), s.st));
+    for (int k = 0; k < m; ++k)
+        KCT_TRY(launch_forward(s.sub[k], s.pad(), KCT_F32, sa_W(s) + sa_off(s, k), KCT_F32, plain, s.st));
+    KCT_TRY(sa_inv_nz(sa_W(s), s.N(), s.st));
+    // V_k = 1 / (A_k^T 1).
+    KCT_TRY(vk_fill(sa_r(s), KCT_F32, s.N(), 1.f, s.st));
+    for (int k = 0; k < m; ++k)
+        KCT_TRY(launch_backward(s.sub[k], sa_r(s) + sa_off(s, k), KCT_F32, sa_V(s, k), KCT_F32, plain, s.st));
+    KCT_TRY(sa_inv_nz(sa_V(s, 0), int64_t(m) * s.M(), s.st));
+    KCT_TRY(vk_fill(s.x, KCT_F32, s.M(), 0.f, s.st));
+    return sa_sc_init(s.S(), s.prm.n_iter, s.prm.lambda, s.st);
+}
+
+kct_status sa_iter(kct_state &s)
+{
+    Plan &p = *s.plan;
+    const int m = sa_m(s);
+    for (int k = 0; k < m; ++k) {
+        Plan &v = s.sub[k];
+        float *r = sa_r(s) + sa_off(s, k);
+        const int64_t nk = int64_t(v.gp.na) * v.gp.nv * v.gp.nu;
+        Epilogue ef; // r_k = b_k - A_k x, with ||r_k||^2 per workgroup
+        ef.c[0] = -1.0;
+        ef.c[1] = 1.0;
+        ef.in1 = sa_b(s) + sa_off(s, k);
+        ef.partials = s.pa();
+        KCT_TRY(launch_pad_volume(p, s.x, KCT_F32, s.pad(), s.st));
+        KCT_TRY(launch_forward(v, s.pad(), KCT_F32, r, KCT_F32, ef, s.st));
+        const Reduced rr = red(s, s.pa(), fwd_num_groups(v), 0);
+        KCT_TRY(sa_sc_res(s.S(), rr.ptr, rr.n, s.hist, k == 0, k == m - 1, s.st));
+        KCT_TRY(sa_mul(r, sa_W(s) + sa_off(s, k), nk, s.st));
+        Epilogue plain;
+        KCT_TRY(launch_backward(v, r, KCT_F32, sa_v(s), KCT_F32, plain, s.st));
+        KCT_TRY(sa_update_x(s.x, sa_v(s), sa_V(s, k), s.M(), s.S(), s.st));
+    }
+    return KCT_OK;
+}
+
 kct_status enqueue_init(kct_state &s)
 {
     switch (s.prm.solver) {
@@ -486,11 +610,34 @@ kct_status enqueue_init(kct_state &s)
     case KCT_IRN_TV_CGLS: return irn_init(s);
     case KCT_AB_GMRES:
     case KCT_BA_GMRES: return gm_init(s);
+    case KCT_SIRT:
+    case KCT_OS_SART: return sa_init(s);
     }
     return fail(KCT_E_INVALID_ARG, "unknown solver");
 }
 
+kct_status solver_iter(kct_state &s);
+
+// One iteration, with the explicit-residual stop rule around it when asked.
 kct_status enqueue_iter(kct_state &s)
+{
+    if (!(s.prm.flags & KCT_FLAG_STOP_ON_RESIDUAL_INCREASE)) return solver_iter(s);
+    Plan &p = *s.plan;
+    float *xp = static_cast<float *>(s.v(4));
+    KCT_TRY(vk_save_x(s.x, xp, s.M(), s.S(), s.st));
+    KCT_TRY(solver_iter(s));
+    Epilogue ef; // b - A x_k, with partial sums of its square
+    ef.c[0] = -1.0;
+    ef.c[1] = 1.0;
+    ef.in1 = s.b;
+    ef.partials = s.pa();
+    KCT_TRY(launch_pad_volume(p, s.x, KCT_F32, s.pad(), s.st));
+    KCT_TRY(launch_forward(p, s.pad(), KCT_F32, s.v(5), KCT_F32, ef, s.st));
+    KCT_TRY(sk_explicit(s.S(), red(s, s.pa(), fwd_num_groups(p), 0), s.hist, s.st));
+    return vk_restore_x(s.x, xp, s.M(), s.S(), s.st);
+}
+
+kct_status solver_iter(kct_state &s)
 {
     switch (s.prm.solver) {
     case KCT_CGLS: return cgls_iter(s);
@@ -500,6 +647,8 @@ kct_status enqueue_iter(kct_state &s)
     case KCT_IRN_TV_CGLS: return irn_iter(s);
     case KCT_AB_GMRES:
     case KCT_BA_GMRES: return gm_iter(s);
+    case KCT_SIRT:
+    case KCT_OS_SART: return sa_iter(s);
     }
     return fail(KCT_E_INVALID_ARG, "unknown solver");
 }
@@ -525,6 +674,7 @@ kct_status kct_solve_workspace_bytes(const kct_plan *plan, const kct_solve_param
 {
     if (!plan || !bytes) return fail(KCT_E_INVALID_ARG, "NULL argument");
     KCT_TRY(check_params(params));
+    KCT_TRY(check_params_plan(*plan, *params));
     *bytes = layout(*plan, *params).total;
     return KCT_OK;
 }
@@ -536,6 +686,7 @@ kct_status kct_state_create(kct_plan *plan, const kct_solve_params *params, cons
     *out = nullptr;
     if (!plan || !d_b || !d_x || !d_ws) return fail(KCT_E_INVALID_ARG, "NULL argument");
     KCT_TRY(check_params(params));
+    KCT_TRY(check_params_plan(*plan, *params));
     const Layout L = layout(*plan, *params);
     if (ws_bytes < L.total) return fail(KCT_E_BUDGET, "workspace smaller than kct_solve_workspace_bytes");
     if (reinterpret_cast<uintptr_t>(d_ws) % ALIGN) return fail(KCT_E_INVALID_ARG, "workspace must be 256-byte aligned");

@@ -30,6 +30,7 @@ import numpy as np
 import torch
 
 from . import Geometry, Plan
+from ._lib import KCT_HIST_COLS
 
 
 @dataclasses.dataclass
@@ -70,17 +71,18 @@ def request_bytes(plan: Plan, req: Request) -> int:
     """Device bytes a request holds while active."""
     ws = plan.workspace_bytes(req.solver, req.n_iter, req.lam, req.vec_dtype)
     x = req.geom.n_voxels * 4
-    hist = max(req.n_iter, 1) * 4 * 8
+    hist = max(req.n_iter, 1) * KCT_HIST_COLS * 8
     return ws + x + hist + plan.device_bytes()
 
 
 class Server:
     def __init__(self, budget_bytes: float = 200e9, device: int = 0, max_active: int = 16,
-                 keep_results: bool = True):
+                 keep_results: bool = True, verbose: bool = False):
         self.budget = int(budget_bytes)
         self.device = torch.device("cuda", device)
         self.max_active = max_active
         self.keep_results = keep_results
+        self.verbose = verbose
         self.log = []
 
     def run(self, requests: list[Request]) -> list[Result]:
@@ -138,6 +140,9 @@ class Server:
                         a.plan.close()
                         used -= a.nbytes
                         self.log.append(("finish", a.req.id, fin, used))
+                        if self.verbose and (len(results) % 8 == 0 or len(results) == len(requests)):
+                            print(f"[serve] batched: {len(results)}/{len(requests)} done at {fin:.1f} s",
+                                  file=sys.stderr, flush=True)
                     else:
                         still.append(a)
                 active = still
@@ -149,7 +154,8 @@ class Server:
         return [results[r.id] for r in sorted(requests, key=lambda r: r.id)]
 
 
-def serve_serial(requests: list[Request], device: int = 0, keep_results: bool = True) -> list[Result]:
+def serve_serial(requests: list[Request], device: int = 0, keep_results: bool = True,
+                 verbose: bool = False) -> list[Result]:
     """Plain per-request path: each request solved alone with kct_solve in
     arrival order; latency includes waiting behind earlier requests."""
     dev = torch.device("cuda", device)
@@ -168,6 +174,8 @@ def serve_serial(requests: list[Request], device: int = 0, keep_results: bool = 
             out[req.id] = Result(req.id, req.arrival, start, fin, x if keep_results else None,
                                  h if keep_results else None)
             plan.close()
+            if verbose and (len(out) % 8 == 0 or len(out) == len(requests)):
+                print(f"[serve] serial: {len(out)}/{len(requests)} done at {fin:.1f} s", file=sys.stderr, flush=True)
     return [out[r.id] for r in sorted(requests, key=lambda r: r.id)]
 
 
@@ -213,6 +221,8 @@ def make_requests(n=64, rate=2.0, seed=5, size_scale=1.0, device=0, det_scale=No
                                      r["seed"])
         plan.close()
         reqs.append(Request(r["id"], r["arrival"], geom, b, r["solver"], r["n_iter"]))
+        if len(reqs) % 8 == 0:
+            print(f"[serve] generated {len(reqs)}/{n} requests", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     return reqs
 
@@ -230,12 +240,12 @@ def main(argv=None):
     reqs = make_requests(args.requests, args.rate, size_scale=args.size_scale)
     work = sum(r.n_iter * r.geom.n_rays for r in reqs)
     print(f"[serve] {len(reqs)} requests, {work / 1e9:.1f} G ray-iterations", file=sys.stderr, flush=True)
-    srv = Server(args.budget_gb * 1e9, max_active=args.max_active, keep_results=False)
+    srv = Server(args.budget_gb * 1e9, max_active=args.max_active, keep_results=False, verbose=True)
     res = srv.run(reqs)
     out = {"batched": summarize(res)}
     print(f"[serve] batched {out['batched']}", file=sys.stderr, flush=True)
     if not args.no_serial:
-        ser = serve_serial(reqs, keep_results=False)
+        ser = serve_serial(reqs, keep_results=False, verbose=True)
         out["serial"] = summarize(ser)
         print(f"[serve] serial {out['serial']}", file=sys.stderr, flush=True)
     out["config"] = {"requests": args.requests, "rate_per_s": args.rate, "size_scale": args.size_scale,

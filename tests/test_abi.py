@@ -44,12 +44,15 @@ def test_header_constants_match_binding():
     assert int(vals["KCT_LAMBDA_DP"]) == _lib.KCT_LAMBDA_DP
     assert int(vals["KCT_AB_GMRES"]) == _lib.KCT_AB_GMRES and int(vals["KCT_BA_GMRES"]) == _lib.KCT_BA_GMRES
     assert int(vals["KCT_BP_MATCHED"]) == _lib.KCT_BP_MATCHED and int(vals["KCT_BP_INTERP"]) == _lib.KCT_BP_INTERP
+    assert int(vals["KCT_SIRT"]) == _lib.KCT_SIRT and int(vals["KCT_OS_SART"]) == _lib.KCT_OS_SART
     assert int(re.search(r"#define KCT_HIST_COLS (\d+)", src).group(1)) == _lib.KCT_HIST_COLS
     for name, code in _lib.STATUS_NAMES.items():
         assert int(vals[code]) == name
     # struct layouts: ctypes sizes equal the C sizes under the x86-64 ABI
     assert ctypes.sizeof(_lib.KctGeometry) == 4 * 3 + 4 + 8 * 6 + 4 * 2 + 8 * 2 + 8 * 2 + 8 + 8
-    assert ctypes.sizeof(_lib.KctSolveParams) == 4 + 4 + 8 + 4 + 4 + 8 + 4 + 4 + 8 + 4 + 4
+    assert ctypes.sizeof(_lib.KctSolveParams) == 4 + 4 + 8 + 4 + 4 + 8 + 4 + 4 + 8 + 4 + 4 + 4 + 4
+    assert int(re.search(r"#define KCT_FLAG_STOP_ON_RESIDUAL_INCREASE (\d+)u", src).group(1)) == \
+        _lib.KCT_FLAG_STOP_ON_RESIDUAL_INCREASE
 
 
 def test_status_strings_and_version():
@@ -89,7 +92,7 @@ def test_invalid_geometry_rejected_without_device():
 def test_null_arguments_rejected():
     lib = _lib.load()
     n = ctypes.c_size_t()
-    p = _lib.KctSolveParams(0, 10, 0.0, 0, 0, 1e-3, 0, 0, 0.0, 0, 0)
+    p = _lib.KctSolveParams(0, 10, 0.0, 0, 0, 1e-3, 0, 0, 0.0, 0, 0, 0, 0)
     assert lib.kct_solve_workspace_bytes(None, ctypes.byref(p), ctypes.byref(n)) == 1
     assert lib.kct_forward(None, None, 0, None, 0, None) == 1
     assert lib.kct_backproject(None, None, 0, None, 0, None) == 1

@@ -345,3 +345,35 @@ def test_os_sart_one_subset_is_sirt_and_solves_consistent_systems():
     x4, h4 = S.os_sart(subs, [b[P] for P in parts], 3000)
     assert np.linalg.norm(x4 - xt) <= 1e-6 * np.linalg.norm(xt)
     assert h4["res"][-1] < 1e-6 * h4["res"][0]
+
+
+def test_explicit_residual_stop_rule_by_hand():
+    """The stop rule (Sec. 3.1.1): residual norms 3, 2, 2, 2.5, 1 stop at the
+    fourth iterate (the first strict increase) and return the third; a
+    sequence that never grows returns its last iterate."""
+    b = np.array([3.0, 0.0])
+    A = lambda x: x  # noqa: E731
+    its = [b - np.array([r, 0.0]) for r in (3.0, 2.0, 2.0, 2.5, 1.0)]
+    k, x, res = S.explicit_residual_stop(A, b, its)
+    assert k == 3 and x is its[2]
+    np.testing.assert_allclose(res, [3.0, 2.0, 2.0, 2.5])
+    k, x, res = S.explicit_residual_stop(A, b, its[:3] + its[4:])
+    assert k is None and x is its[-1] and len(res) == 4
+
+
+def test_stop_rule_quiet_for_exact_cgls_and_fires_for_a_mismatched_adjoint():
+    """Exact-arithmetic CGLS minimises ||b - A x|| over nested spaces, so the
+    rule never fires; with a back projector that is not A^T (the situation
+    Sec. 3.1.2 blames for growing residuals) it does."""
+    rng = np.random.default_rng(5)
+    M = rng.standard_normal((40, 25))
+    b = rng.standard_normal(40)
+    A, AT = (lambda x: M @ x), (lambda y: M.T @ y)
+    its = [S.cgls(A, AT, b, k)[0] for k in range(1, 26)]
+    k, _, res = S.explicit_residual_stop(A, b, its)
+    assert k is None and np.all(np.diff(res) <= 1e-12 * res[0])
+    E = rng.standard_normal((25, 40))
+    B = lambda y: M.T @ y + 0.6 * (E @ y)  # noqa: E731
+    its = [S.cgls(A, B, b, k)[0] for k in range(1, 26)]
+    k, x, res = S.explicit_residual_stop(A, b, its)
+    assert k is not None and res[k] > res[k - 1] and x is its[k - 1]
