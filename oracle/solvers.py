@@ -31,6 +31,10 @@ works it cites for each method).  Equations are named by their labels:
   * IRN-TV    -- Sec. 2.3, eqs. (TV), (TV_reweighted), (TV_approx) and
                  Sec. 2.3.1: reweighted quadratic majorants of isotropic TV, each
                  solved by CGLS on [A; lam L D].
+  * hybrid fLSQR-TV -- Sec. 2.3.2, eq. (TV_standard_form): the same weights
+                 as a changing right preconditioner (the A-weighted
+                 pseudoinverse of L D) in a flexible Golub-Kahan process, with
+                 the hybrid projected Tikhonov solve.
 """
 from __future__ import annotations
 
@@ -311,17 +315,41 @@ def lambda_dp(s, c, target):
     return float(10.0 ** (0.5 * (lo + hi)))
 
 
+def projected_tikhonov(Bk, beta1, rule, lam, noise_level=None):
+    """Tikhonov solution of the projected problem
+    min ||Bk y - beta1 e1||^2 + lam_k^2 ||y||^2 for a (k+1) x k matrix Bk.
+
+    lam_k is ``lam`` (rule "fixed"), the GCV minimiser (rule "gcv"), or the
+    discrepancy-principle root for the relative noise level ``noise_level``
+    (rule "dp"), from the SVD of Bk.  y = Q diag(s / (s^2 + lam_k^2)) c[:k].
+    Returns (y, lam_k, res) with res = ||[beta1 e1; 0] - [Bk; lam_k I] y||
+    (beta1 when lam_k is infinite and y = 0).
+    """
+    k = Bk.shape[1]
+    s, Q, c = _projected_svd(Bk, beta1)
+    if rule == "gcv":
+        lk = lambda_gcv(s, c)
+    elif rule == "dp":
+        lk = lambda_dp(s, c, (noise_level * beta1) ** 2)
+    else:
+        lk = float(lam)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        g = np.where(s > 0, s / (s * s + lk * lk), 0.0) if np.isfinite(lk) else np.zeros_like(s)
+    y = Q @ (g * c[:k])
+    if not np.isfinite(lk):
+        return y, lk, float(beta1)
+    return y, lk, float(np.sqrt(projected_residual2(s, c, lk) + lk * lk * float(np.dot(y, y))))
+
+
 def hybrid_lsqr(A, AT, b, n_iter, lam, rule="fixed", noise_level=None):
     """x_k = V_k y_k, y_k = argmin ||beta1 e1 - B_k y||^2 + lam_k^2 ||y||^2
     (Sec. 2.2.1, eq. (hybrid_LSQR)).
 
-    lam_k is ``lam`` (rule "fixed"), the GCV minimiser (rule "gcv"), or the
-    discrepancy-principle root for the relative noise level
-    ``noise_level`` = ||e|| / ||b|| (rule "dp"), recomputed at every k from
-    the SVD of B_k.  y_k = Q diag(s / (s^2 + lam_k^2)) c[:k].  hist: 'res' =
-    ||[beta1 e1; 0] - [B_k; lam_k I] y_k|| (the projected Tikhonov residual,
-    equal to the augmented-system residual while U_{k+1} is orthonormal),
-    'lam' = lam_k, 'y' = the last y_k.
+    lam_k is recomputed at every k by ``projected_tikhonov`` from the SVD of
+    B_k (rule "fixed", "gcv" or "dp"; ``noise_level`` = ||e|| / ||b||).
+    hist: 'res' = ||[beta1 e1; 0] - [B_k; lam_k I] y_k|| (the projected
+    Tikhonov residual, equal to the augmented-system residual while U_{k+1}
+    is orthonormal), 'lam' = lam_k, 'y' = the last y_k.
     """
     if rule not in ("fixed", "gcv", "dp"):
         raise ValueError(rule)
@@ -329,19 +357,8 @@ def hybrid_lsqr(A, AT, b, n_iter, lam, rule="fixed", noise_level=None):
     hist = {"res": [], "lam": []}
     y = np.zeros(0)
     for k in range(1, B.shape[1] + 1):
-        s, Q, c = _projected_svd(B[: k + 1, :k], beta1)
-        if rule == "gcv":
-            lk = lambda_gcv(s, c)
-        elif rule == "dp":
-            lk = lambda_dp(s, c, (noise_level * beta1) ** 2)
-        else:
-            lk = float(lam)
-        with np.errstate(invalid="ignore", divide="ignore"):
-            g = np.where(s > 0, s / (s * s + lk * lk), 0.0) if np.isfinite(lk) else np.zeros_like(s)
-        y = Q @ (g * c[:k])
-        pen = 0.0 if not np.isfinite(lk) else lk * lk * float(np.dot(y, y))
-        hist["res"].append(float(np.sqrt(projected_residual2(s, c, lk) + pen)) if np.isfinite(lk)
-                           else float(beta1))
+        y, lk, res = projected_tikhonov(B[: k + 1, :k], beta1, rule, lam, noise_level)
+        hist["res"].append(res)
         hist["lam"].append(lk)
     x = np.zeros_like(Vs[0]) if Vs else np.zeros_like(AT(np.asarray(b, dtype=np.float64)))
     for i, yi in enumerate(y):
@@ -594,3 +611,124 @@ def irn_tv_cgls(A, AT, b, shape, n_outer, n_inner, lam, eps):
             hist["res"].append(_nrm(r1))
         hist["tv"].append(tv(x))
     return x, {k: np.asarray(v) for k, v in hist.items()}
+
+
+# ---------------------------------------------------------------------------
+# Hybrid fLSQR-TV (Sec. 2.3.2, eq. (TV_standard_form)).
+#
+# Each problem of the IRN sequence, eq. (TV_approx) with L = L^(k), is put in
+# standard form with the A-weighted pseudoinverse of L D:
+#     x = x0 + (L D)_A^dagger ybar,  (L D)_A^dagger = E (L D)^dagger,
+# where the null space of L D is the constants (D x = 0 only for constant x on
+# a connected grid, and L is a positive diagonal), so with a = A 1:
+#     x0 = 1 (a^T b) / (a^T a),  bbar = b - A x0,
+#     E z = z - 1 (a^T A z) / (a^T a)   (the oblique projector I - (A N)^dagger A
+#                                        restricted to N = span{1}),
+# and (L D)^dagger v = K^dagger D^T L v with K = D^T L^2 D (a weighted
+# Neumann Laplacian, SPD on the complement of the constants).  Reading: K^dagger
+# is applied by ``n_inner`` CG steps from zero (the right-hand sides are
+# orthogonal to the constants, so the iterates stay there).  The changing
+# preconditioner P_k = E (L^(k) D)^dagger enters a flexible Golub-Kahan process:
+#     v_k  = P_k^T A^T u_k orthonormalised against v_1..v_{k-1} (gradient space),
+#     z_k  = P_k v_k,
+#     A z_k = sum_{i <= k+1} M[i, k] u_i  (u_{k+1} orthonormalised),
+# so A Z_k = U_{k+1} M_k with M_k upper Hessenberg, and
+#     x_k = x0 + Z_k y_k,  y_k = argmin ||M_k y - beta1 e1||^2 + lam_k^2 ||y||^2
+# (||y|| = ||V_k y||, the standard-form penalty).  L^(1) = I and L^(k+1) are the
+# IRN weights of x_k (reweighted at every iteration).
+# ---------------------------------------------------------------------------
+
+
+def weighted_laplacian(w2, s):
+    """K s = D^T (w2 D s) with w2 = L^2 per voxel (all three components)."""
+    return grad_T(w2[None] * grad(s))
+
+
+def cg_weighted_laplacian(w2, rhs, n_inner):
+    """``n_inner`` CG steps on K t = rhs from t = 0 (Hestenes-Stiefel CG) on
+    the complement of the constants, where K is SPD: the residual has its mean
+    removed at every step, so rounding cannot feed the null space of K (which
+    would make the system inconsistent and CG diverge once converged).  Stops
+    early when the residual vanishes."""
+    t = np.zeros_like(rhs)
+    r = rhs - np.mean(rhs)
+    p = r.copy()
+    gamma = _dot(r, r)
+    for _ in range(n_inner):
+        if gamma == 0.0:
+            break
+        q = weighted_laplacian(w2, p)
+        alpha = gamma / _dot(p, q)
+        t = t + alpha * p
+        r = r - alpha * q
+        r = r - np.mean(r)
+        gamma_new = _dot(r, r)
+        p = r + (gamma_new / gamma) * p
+        gamma = gamma_new
+    return t
+
+
+def hybrid_flsqr_tv(A, AT, b, shape, n_iter, lam, eps, n_inner, rule="fixed", noise_level=None, reweight=True):
+    """Hybrid fLSQR with TV weights (Sec. 2.3.2), as read above.
+
+    ``lam``/``rule``/``noise_level`` choose lam_k on the projected problem as
+    in hybrid LSQR; ``n_inner`` CG steps apply each pseudoinverse;
+    ``reweight=False`` keeps L = I throughout (then the method is hybrid LSQR
+    with full reorthogonalisation on the standard-form problem of
+    min ||A x - b||^2 + lam^2 ||D x||^2).  Returns (x, hist) with hist 'res'
+    (projected Tikhonov residual per iteration), 'lam' (lam_k), and the
+    process's 'U', 'V', 'Z', 'M' for the tests.
+    """
+    if rule not in ("fixed", "gcv", "dp"):
+        raise ValueError(rule)
+    b = np.asarray(b, dtype=np.float64)
+    a = A(np.ones(shape))
+    ca = _dot(a, a)
+    c0 = _dot(a, b) / ca if ca > 0.0 else 0.0
+    x0 = np.full(shape, c0)
+    g = AT(a)
+    bbar = b - c0 * a
+
+    def E(z):
+        return z - (_dot(g, z) / ca if ca > 0.0 else 0.0)
+
+    def ET(w):
+        return w - g * (float(np.sum(w)) / ca) if ca > 0.0 else w
+
+    u, beta1 = _normalise(bbar)
+    U, V, Z = [u], [], []
+    M = np.zeros((n_iter + 1, n_iter))
+    hist = {"res": [], "lam": []}
+    x = x0.copy()
+    for k in range(n_iter):
+        if beta1 == 0.0:
+            break
+        Lw = irn_weights(x, eps) if (reweight and k > 0) else np.ones(shape)
+        w2 = Lw * Lw
+        v = Lw[None] * grad(cg_weighted_laplacian(w2, ET(AT(U[k])), n_inner))
+        for vi in V:
+            v = v - _dot(v, vi) * vi
+        v, tkk = _normalise(v)
+        if tkk == 0.0:
+            break
+        V.append(v)
+        z = E(cg_weighted_laplacian(w2, grad_T(Lw[None] * v), n_inner))
+        Z.append(z)
+        q = A(z)
+        for i in range(k + 1):
+            M[i, k] = _dot(q, U[i])
+            q = q - M[i, k] * U[i]
+        q, M[k + 1, k] = _normalise(q)
+        U.append(q)
+        y, lk, res = projected_tikhonov(M[: k + 2, : k + 1], beta1, rule, lam, noise_level)
+        hist["res"].append(res)
+        hist["lam"].append(lk)
+        x = x0.copy()
+        for i, yi in enumerate(y):
+            x = x + yi * Z[i]
+        if M[k + 1, k] == 0.0:
+            break
+    kk = len(Z)
+    hist.update(res=np.asarray(hist["res"]), lam=np.asarray(hist["lam"]), U=U, V=V, Z=Z,
+                M=M[: kk + 1, :kk], x0=x0)
+    return x, hist
