@@ -185,6 +185,48 @@ def precision_report(plan, b, xt, torch, wl):
     return out
 
 
+# Every solver of the library on the same data, 30 iterations each (IRN-TV:
+# 3 outer x 10 inner): wall time per iteration and error against the phantom.
+SOLVER_RUNS = [
+    ("cgls", "cgls", 30, 0.0, {}),
+    ("lsqr", "lsqr", 30, 0.0, {}),
+    ("lsmr", "lsmr", 30, 0.0, {}),
+    ("hybrid_lsqr_gcv", "hybrid_lsqr", 30, 0.0, {"lam_rule": "gcv"}),
+    ("ab_gmres_interp", "ab_gmres", 30, 0.0, {"backprojector": "interp"}),
+    ("ba_gmres_interp", "ba_gmres", 30, 0.0, {"backprojector": "interp"}),
+    ("sirt", "sirt", 30, 1.0, {}),
+    ("os_sart_10_subsets", "os_sart", 30, 1.0, {"n_subsets": 10}),
+    ("irn_tv_cgls_3x10", "irn_tv_cgls", 0, 1.0, {"tv_outer": 3, "tv_inner": 10, "tv_eps": 1e-3}),
+    ("hybrid_flsqr_tv", "hybrid_flsqr_tv", 30, 0.1, {"tv_inner": 10, "tv_eps": 1e-3}),
+]
+
+
+def solver_report(plan, b, xt, torch, scale=1.0):
+    """``scale`` shrinks every iteration count (profiling runs)."""
+    out = {}
+    nx = torch.linalg.vector_norm(xt)
+    for label, solver, n, lam, kw in SOLVER_RUNS:
+        kw = dict(kw)
+        n = max(1, int(round(n * scale))) if n else 0
+        if solver == "irn_tv_cgls":
+            kw["tv_outer"] = max(1, int(round(kw["tv_outer"] * scale)))
+        iters = kw["tv_outer"] * kw["tv_inner"] if solver == "irn_tv_cgls" else n
+        log(f"[bench] solver {label}")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, h = plan.solve(b, solver, n, lam, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        h = h.cpu().numpy()
+        out[label] = {"iterations": iters, "lambda": lam, "s": round(dt, 3), "ms_per_iter": round(1e3 * dt / iters, 2),
+                      "rel_err_vs_phantom": round(float(torch.linalg.vector_norm(x - xt) / nx), 4),
+                      "last_hist_res": float(h[-1, 0]), "last_lambda": float(h[-1, 4])}
+        log(f"[bench]   {out[label]}")
+        del x, h
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -206,6 +248,11 @@ def main():
     ap.add_argument("--operators-only", action="store_true",
                     help="projector timings and a short IRN-TV run only (for the largest workloads); prints its "
                          "own JSON line")
+    ap.add_argument("--solvers", action="store_true",
+                    help="report every solver's time per iteration and error vs the phantom instead of the "
+                         "benchmark line")
+    ap.add_argument("--solver-scale", type=float, default=1.0,
+                    help="with --solvers: multiply every iteration count (e.g. 0.34 for a profiling run)")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only run the projectors (and a plain 1 GiB copy for counter calibration) "
                          "a few times, for rocprofv3; prints no JSON line")
@@ -264,6 +311,10 @@ def main():
                                               synth.WORKLOADS[wl]["seed"])
     torch.cuda.synchronize()
 
+    if args.solvers:
+        rep = solver_report(plan, b, xt, torch, args.solver_scale)
+        print(json.dumps({"report": "solvers", "workload": wl, "data": "synthetic", "results": rep}), flush=True)
+        return
     if args.precision:
         rep = precision_report(plan, b, xt, torch, wl)
         print(json.dumps({"report": "16-bit vector storage vs the FP32 path", "workload": wl, "data": "synthetic",

@@ -151,8 +151,18 @@ typedef enum kct_solver {
                             k+1 volume-space basis vectors                         */
     KCT_SIRT = 7,        /* Sec. 3's algebraic baseline: x += lam V A^T W (b - A x),
                             W = 1 / (A 1), V = 1 / (A^T 1); lambda in (0, 2)       */
-    KCT_OS_SART = 8      /* SIRT's update over n_subsets ordered angle subsets per
+    KCT_OS_SART = 8,     /* SIRT's update over n_subsets ordered angle subsets per
                             iteration (subset s: angles a with a mod n_subsets = s) */
+    KCT_HYBRID_FLSQR_TV = 9 /* Sec. 2.3.2, eq. (TV_standard_form): hybrid flexible
+                            LSQR for the TV problem.  The IRN weights L_k of the
+                            current iterate enter as the changing right
+                            preconditioner E (L_k D)^+ (the A-weighted
+                            pseudoinverse; E removes the A-weighted constant
+                            part, x0 is the best constant), with (L_k D)^+
+                            applied by tv_inner CG steps on D^T L_k^2 D.  Stores
+                            n_iter gradient-space vectors (3 volumes each), n_iter
+                            volumes and n_iter+1 projections; lambda_k fixed or
+                            chosen per iteration (kct_lambda_rule); FP32 only */
 } kct_solver;
 
 /* The back projector B of AB-/BA-GMRES.  Every other solver uses A^T. */
@@ -161,8 +171,9 @@ typedef enum kct_backprojector {
     KCT_BP_INTERP = 1   /* the interpolating B of kct_backproject_interp          */
 } kct_backprojector;
 
-/* How hybrid LSQR sets the Tikhonov parameter lambda_k of its projected
- * problem (Sec. 2.2.2).  Every other solver takes KCT_LAMBDA_FIXED.
+/* How hybrid LSQR and hybrid fLSQR-TV set the Tikhonov parameter lambda_k of
+ * their projected problem (Sec. 2.2.2).  Every other solver takes
+ * KCT_LAMBDA_FIXED.
  *   FIXED: lambda_k = params.lambda.
  *   GCV:   lambda_k minimises the GCV function of the projected problem
  *          (B_k, ||b|| e_1), searched on a log grid sigma_max * 10^[-7, 1]
@@ -170,7 +181,8 @@ typedef enum kct_backprojector {
  *   DP:    lambda_k makes the projected residual equal noise_level * ||b||
  *          (discrepancy principle); 0 while even lambda = 0 leaves a larger
  *          residual, +inf (x = 0) when noise_level >= 1.
- * Both use the SVD of B_k (one-sided Jacobi in FP64 on the device). */
+ * Both use the SVD of B_k (one-sided Jacobi in FP64 on the device); for
+ * fLSQR-TV B_k is the upper Hessenberg matrix of the flexible process. */
 typedef enum kct_lambda_rule {
     KCT_LAMBDA_FIXED = 0,
     KCT_LAMBDA_GCV = 1,
@@ -180,12 +192,16 @@ typedef enum kct_lambda_rule {
 /* Columns of one history row (FP64), one row per iteration (for IRN-TV: per
  * inner iteration).
  *   [0] residual norm the method recurs: CGLS ||b - A x_k||, LSQR and hybrid
- *       ||[b;0] - [A; lam I] x_k||, LSMR ||[A; lam I]^T r_k||, IRN-TV ||b - A x||,
+ *       ||[b;0] - [A; lam I] x_k||, fLSQR-TV the projected
+ *       ||[bbar;0] - [A Z_k; lam I] y_k||, LSMR ||[A; lam I]^T r_k||,
+ *       IRN-TV ||b - A x||,
  *       AB-GMRES ||b - A x_k||, BA-GMRES ||B (b - A x_k)||, SIRT ||b - A x_k||
  *       before update k+1, OS-SART sqrt(sum_s ||b_s - A_s x||^2) with each
  *       term taken just before subset s updates x;
  *   [1] alpha_k; [2] beta_k (the method's own two leading scalars; GMRES:
- *       H[k+1, k] and the k-th diagonal entry of the rotated Hessenberg matrix);
+ *       H[k+1, k] and the k-th diagonal entry of the rotated Hessenberg matrix;
+ *       fLSQR-TV: the norm of the new gradient-space vector before it is
+ *       normalised and M[k+1, k]);
  *   [3] 1 if the method had broken down (zero norm) by this iteration, 2 if a
  *       scalar became non-finite, 3 if the explicit residual rule stopped it,
  *       else 0;
@@ -198,8 +214,9 @@ typedef struct kct_solve_params {
     int32_t n_iter;    /* iterations (IRN-TV: ignored, tv_outer*tv_inner used)   */
     double lambda;     /* Tikhonov damping (CGLS/LSQR/LSMR/hybrid) or TV weight  */
     int32_t tv_outer;  /* IRN-TV outer iterations                               */
-    int32_t tv_inner;  /* IRN-TV inner CGLS iterations per outer iteration       */
-    double tv_eps;     /* IRN-TV smoothing epsilon of the weights                */
+    int32_t tv_inner;  /* IRN-TV: inner CGLS iterations per outer iteration;
+                          fLSQR-TV: CG steps per pseudoinverse application   */
+    double tv_eps;     /* IRN-TV, fLSQR-TV: smoothing epsilon of the weights     */
     int32_t vec_dtype; /* storage of the vectors the projectors read and write:
                           KCT_F32, KCT_BF16 or KCT_F16; x is always FP32       */
     int32_t lambda_rule; /* kct_lambda_rule; not FIXED only for hybrid LSQR      */

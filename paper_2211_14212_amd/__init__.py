@@ -25,7 +25,7 @@ __all__ = ["Geometry", "Plan", "State", "SOLVERS", "require_gpu", "KctError", "d
 
 SOLVERS = {"cgls": KCT_CGLS, "lsqr": KCT_LSQR, "lsmr": KCT_LSMR, "hybrid_lsqr": KCT_HYBRID_LSQR,
            "irn_tv_cgls": KCT_IRN_TV_CGLS, "ab_gmres": _lib.KCT_AB_GMRES, "ba_gmres": _lib.KCT_BA_GMRES,
-           "sirt": _lib.KCT_SIRT, "os_sart": _lib.KCT_OS_SART}
+           "sirt": _lib.KCT_SIRT, "os_sart": _lib.KCT_OS_SART, "hybrid_flsqr_tv": _lib.KCT_HYBRID_FLSQR_TV}
 _DT = {torch.float32: KCT_F32, torch.bfloat16: KCT_BF16, torch.float16: KCT_F16}
 
 
@@ -210,8 +210,9 @@ class Plan:
               stream=None, **tv):
         """Run `solver` from x0 = 0 for `n_iter` iterations.  Returns (x, history).
 
-        Keyword options: tv_outer, tv_inner, tv_eps (IRN-TV); lam_rule
-        ("fixed", "gcv" or "dp") and noise_level (hybrid LSQR); backprojector
+        Keyword options: tv_outer, tv_inner, tv_eps (IRN-TV; fLSQR-TV takes
+        tv_inner = CG steps per pseudoinverse and tv_eps); lam_rule
+        ("fixed", "gcv" or "dp") and noise_level (hybrid LSQR, fLSQR-TV); backprojector
         ("matched" or "interp", AB-/BA-GMRES); n_subsets (OS-SART; lam is
         the relaxation of SIRT and OS-SART); stop_on_residual_increase
         (CGLS, LSQR, LSMR).  history is an

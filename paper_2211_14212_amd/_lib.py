@@ -20,7 +20,7 @@ STATUS_NAMES = {0: "KCT_OK", 1: "KCT_E_INVALID_ARG", 2: "KCT_E_GEOMETRY", 3: "KC
 KCT_F32, KCT_BF16, KCT_F16 = 0, 1, 2
 # kct_solver
 (KCT_CGLS, KCT_LSQR, KCT_LSMR, KCT_HYBRID_LSQR, KCT_IRN_TV_CGLS, KCT_AB_GMRES, KCT_BA_GMRES, KCT_SIRT,
- KCT_OS_SART) = range(9)
+ KCT_OS_SART, KCT_HYBRID_FLSQR_TV) = range(10)
 # kct_backprojector
 KCT_BP_MATCHED, KCT_BP_INTERP = 0, 1
 # flags

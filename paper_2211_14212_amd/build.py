@@ -14,6 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkct.so")
 SOURCES = ["api.hip", "proj_fwd.hip", "proj_bwd.hip", "proj_interp.hip", "krylov_kernels.hip", "tv_kernels.hip", "gmres.hip",
            "sart.hip",
+           "flsqr.hip",
            "solve.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

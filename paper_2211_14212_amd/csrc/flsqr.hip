@@ -1,0 +1,472 @@
+// Hybrid fLSQR-TV (paper Sec. 2.3.2, eq. (TV_standard_form)): vector and
+// scalar kernels of the standard-form transform and of the inner CG.
+//
+// The TV weights L (one factor per voxel, shared by the three gradient
+// components) define the changing preconditioner P = E (L D)^+ with
+//   (L D)^+ v = K^+ D^T L v,   K = D^T L^2 D (weighted Neumann Laplacian),
+//   E z = z - 1 (g^T z) / (a^T a),   a = A 1, g = A^T a,
+// and its transpose P^T w = L D K^+ E^T w with E^T w = w - g (1^T w)/(a^T a).
+// K^+ is applied by CG from zero on the complement of the constants, where K
+// is SPD: every step removes the mean of the residual (folded into the
+// direction update), so rounding cannot drive the iterate along the null
+// space.  D is the forward difference with a zero last difference per axis,
+// as in IRN-TV.  Volumes are x-fastest; gradient-space vectors are planar
+// (component c of voxel e at c*M + e).  All vector kernels are one thread per
+// voxel in a grid-stride loop and bound by HBM bandwidth; the stencil reads
+// of the six neighbours come from L2.
+
+#include "flsqr.hpp"
+
+#include <algorithm>
+
+namespace kct {
+
+namespace {
+
+struct Dims {
+    int nx, ny, nz;
+    int64_t M;
+};
+
+Dims dims(const Plan &p) { return Dims{p.gp.nx, p.gp.ny, p.gp.nz, p.n_vox()}; }
+
+// Fixed-order block sum (4 waves of 64).
+__device__ inline double block_sum(double v, double *red)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    return ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+// Fixed-order sum of n partials by one workgroup (result on thread 0).
+__device__ inline double sum_parts(const double *p, int64_t n, double *red)
+{
+    double s = 0.0;
+    for (int64_t e = threadIdx.x; e < n; e += 256) s += p[e];
+    return block_sum(s, red);
+}
+
+__device__ inline bool finite(double v) { return v == v && v - v == 0.0; }
+
+#define FL_LOOP(e, n) for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < (n); e += int64_t(gridDim.x) * 256)
+
+__global__ __launch_bounds__(256) void k_fl_lap(const float *__restrict__ p, const float *__restrict__ Lw, Dims d,
+                                                float *__restrict__ q, double *parts)
+{
+    __shared__ double red[4];
+    const int64_t sxy = int64_t(d.nx) * d.ny;
+    double acc = 0.0;
+    FL_LOOP(e, d.M)
+    {
+        const int i = int(e % d.nx), j = int((e / d.nx) % d.ny), k = int(e / sxy);
+        const float c = p[e], le = Lw[e], we = le * le;
+        float t = 0.f;
+        if (i < d.nx - 1) t -= we * (p[e + 1] - c);
+        if (i > 0) {
+            const float l = Lw[e - 1];
+            t += l * l * (c - p[e - 1]);
+        }
+        if (j < d.ny - 1) t -= we * (p[e + d.nx] - c);
+        if (j > 0) {
+            const float l = Lw[e - d.nx];
+            t += l * l * (c - p[e - d.nx]);
+        }
+        if (k < d.nz - 1) t -= we * (p[e + sxy] - c);
+        if (k > 0) {
+            const float l = Lw[e - sxy];
+            t += l * l * (c - p[e - sxy]);
+        }
+        q[e] = t;
+        acc += double(c) * double(t);
+    }
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) parts[blockIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_fl_cg_update(float *__restrict__ t, float *__restrict__ r,
+                                                      const float *__restrict__ p, const float *__restrict__ q,
+                                                      int64_t n, const double *S, double *psum, double *psq)
+{
+    __shared__ double red[4];
+    const double alpha = S[S_CG_ALPHA];
+    double s1 = 0.0, s2 = 0.0;
+    FL_LOOP(e, n)
+    {
+        t[e] = float(double(t[e]) + alpha * p[e]);
+        const float v = float(double(r[e]) - alpha * q[e]);
+        r[e] = v;
+        s1 += v;
+        s2 += double(v) * v;
+    }
+    s1 = block_sum(s1, red);
+    s2 = block_sum(s2, red);
+    if (threadIdx.x == 0) {
+        psum[blockIdx.x] = s1;
+        psq[blockIdx.x] = s2;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fl_cg_dir(float *__restrict__ r, float *__restrict__ p, int64_t n,
+                                                   const double *S, int first)
+{
+    const double mu = S[S_CG_MU], beta = S[S_CG_BETA];
+    FL_LOOP(e, n)
+    {
+        const float v = float(double(r[e]) - mu);
+        r[e] = v;
+        p[e] = first ? v : float(v + beta * p[e]);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fl_dtl(const float *__restrict__ v3, const float *__restrict__ Lw, Dims d,
+                                                float *__restrict__ out, double *psum, double *psq)
+{
+    __shared__ double red[4];
+    const int64_t sxy = int64_t(d.nx) * d.ny;
+    double s1 = 0.0, s2 = 0.0;
+    FL_LOOP(e, d.M)
+    {
+        const int i = int(e % d.nx), j = int((e / d.nx) % d.ny), k = int(e / sxy);
+        const float le = Lw[e];
+        float t = 0.f;
+        if (i < d.nx - 1) t -= le * v3[e];
+        if (i > 0) t += Lw[e - 1] * v3[e - 1];
+        if (j < d.ny - 1) t -= le * v3[d.M + e];
+        if (j > 0) t += Lw[e - d.nx] * v3[d.M + e - d.nx];
+        if (k < d.nz - 1) t -= le * v3[2 * d.M + e];
+        if (k > 0) t += Lw[e - sxy] * v3[2 * d.M + e - sxy];
+        out[e] = t;
+        s1 += t;
+        s2 += double(t) * t;
+    }
+    s1 = block_sum(s1, red);
+    s2 = block_sum(s2, red);
+    if (threadIdx.x == 0) {
+        psum[blockIdx.x] = s1;
+        psq[blockIdx.x] = s2;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fl_sum(const float *__restrict__ v, int64_t n, double *parts)
+{
+    __shared__ double red[4];
+    double s = 0.0;
+    FL_LOOP(e, n) s += v[e];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) parts[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_fl_axpy_sum(float *__restrict__ r, const float *__restrict__ g, int64_t n,
+                                                     const double *S, int ci, double *psum, double *psq)
+{
+    __shared__ double red[4];
+    const double c = S[ci];
+    double s1 = 0.0, s2 = 0.0;
+    FL_LOOP(e, n)
+    {
+        const float v = float(double(r[e]) - c * g[e]);
+        r[e] = v;
+        s1 += v;
+        s2 += double(v) * v;
+    }
+    s1 = block_sum(s1, red);
+    s2 = block_sum(s2, red);
+    if (threadIdx.x == 0) {
+        psum[blockIdx.x] = s1;
+        psq[blockIdx.x] = s2;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fl_shift(float *__restrict__ out, const float *__restrict__ in, int64_t n,
+                                                  const double *S, int ci)
+{
+    const double c = S[ci];
+    FL_LOOP(e, n) out[e] = float(double(in[e]) - c);
+}
+
+__global__ __launch_bounds__(256) void k_fl_fill_s(float *__restrict__ out, int64_t n, const double *S, int ci)
+{
+    const float c = float(S[ci]);
+    FL_LOOP(e, n) out[e] = c;
+}
+
+__global__ __launch_bounds__(256) void k_fl_bbar(float *__restrict__ out, const float *__restrict__ b,
+                                                 const float *__restrict__ a, int64_t n, const double *S,
+                                                 double *parts)
+{
+    __shared__ double red[4];
+    const double c = S[S_P0];
+    double s = 0.0;
+    FL_LOOP(e, n)
+    {
+        const float v = float(double(b[e]) + c * a[e]);
+        out[e] = v;
+        s += double(v) * v;
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) parts[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_fl_combine(float *__restrict__ x, const float *__restrict__ Z, int64_t n,
+                                                    const double *__restrict__ coef, const double *S)
+{
+    const int k = int(S[S_KGK]);
+    const double c0 = S[S_FL_C0];
+    FL_LOOP(e, n)
+    {
+        double s = c0;
+        for (int i = 0; i < k; ++i) s += coef[i] * double(Z[int64_t(i) * n + e]);
+        x[e] = float(s);
+    }
+}
+
+// ------------------------------------------------------------ scalar kernels
+
+// x0 = c0 1 with c0 = a^T b / a^T a (0 when A 1 = 0); S_P0 = -c0 for bbar.
+__global__ __launch_bounds__(256) void k_sc_fl_init(double *S, const double *pca, int64_t nca, const double *pab,
+                                                    int64_t nab, int n_iter, double lam)
+{
+    __shared__ double red[4];
+    const double ca = sum_parts(pca, nca, red);
+    const double ab = sum_parts(pab, nab, red);
+    if (threadIdx.x != 0) return;
+    const double c0 = ca > 0.0 ? ab / ca : 0.0;
+    S[S_ITER] = n_iter;
+    S[S_HROW] = 0.0;
+    S[S_KGK] = 0.0;
+    S[S_DONE] = finite(c0) ? 0.0 : 2.0;
+    S[S_LAMBDA] = lam;
+    S[S_HLAM] = lam;
+    S[S_FL_CA] = ca;
+    S[S_FL_C0] = finite(c0) ? c0 : 0.0;
+    S[S_P0] = finite(c0) ? -c0 : 0.0;
+}
+
+// beta_1 = ||bbar||; S_V0 = 1 / beta_1 normalises u_1.
+__global__ __launch_bounds__(256) void k_sc_fl_beta1(double *S, const double *p, int64_t n)
+{
+    __shared__ double red[4];
+    const double b2 = sum_parts(p, n, red);
+    if (threadIdx.x != 0) return;
+    const double beta = sqrt(b2);
+    S[S_BETA] = beta;
+    if (S[S_DONE] == 0.0) S[S_DONE] = !finite(beta) ? 2.0 : (beta > 0.0 ? 0.0 : 1.0);
+    S[S_V0] = S[S_DONE] == 0.0 ? 1.0 / beta : 0.0;
+}
+
+// S[ci] = dot / a^T a (the E or E^T correction), 0 once done.
+__global__ __launch_bounds__(256) void k_sc_fl_ecoef(double *S, const double *p, int64_t n, int ci)
+{
+    __shared__ double red[4];
+    const double d = sum_parts(p, n, red);
+    if (threadIdx.x != 0) return;
+    const double ca = S[S_FL_CA];
+    const double c = (S[S_DONE] == 0.0 && ca > 0.0) ? d / ca : 0.0;
+    S[ci] = finite(c) ? c : 0.0;
+}
+
+// Inner CG start from the sums of the right-hand side r: mu = mean(r),
+// gamma = ||r - mu||^2.
+__global__ __launch_bounds__(256) void k_sc_fl_cg_init(double *S, const double *ps, int64_t ns, const double *pq,
+                                                       int64_t nq, int64_t n)
+{
+    __shared__ double red[4];
+    const double s1 = sum_parts(ps, ns, red);
+    const double s2 = sum_parts(pq, nq, red);
+    if (threadIdx.x != 0) return;
+    const double mu = s1 / double(n);
+    const double g = s2 - double(n) * mu * mu;
+    const bool ok = finite(mu) && finite(g);
+    S[S_CG_MU] = ok ? mu : 0.0;
+    S[S_CG_GAMMA] = ok ? fmax(g, 0.0) : 0.0;
+    S[S_CG_BETA] = 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_sc_fl_cg_alpha(double *S, const double *p, int64_t n)
+{
+    __shared__ double red[4];
+    const double pq = sum_parts(p, n, red);
+    if (threadIdx.x != 0) return;
+    const double g = S[S_CG_GAMMA];
+    const double a = (g > 0.0 && pq > 0.0) ? g / pq : 0.0;
+    S[S_CG_ALPHA] = finite(a) ? a : 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_sc_fl_cg_beta(double *S, const double *ps, int64_t ns, const double *pq,
+                                                       int64_t nq, int64_t n)
+{
+    __shared__ double red[4];
+    const double s1 = sum_parts(ps, ns, red);
+    const double s2 = sum_parts(pq, nq, red);
+    if (threadIdx.x != 0) return;
+    const double mu = s1 / double(n);
+    const double gn = fmax(s2 - double(n) * mu * mu, 0.0);
+    const double g = S[S_CG_GAMMA];
+    const bool ok = finite(mu) && finite(gn) && g > 0.0 && S[S_CG_ALPHA] > 0.0;
+    S[S_CG_MU] = ok ? mu : 0.0;
+    S[S_CG_BETA] = ok ? gn / g : 0.0;
+    S[S_CG_GAMMA] = ok ? gn : 0.0;
+}
+
+// Norm of the new gradient-space vector: a zero norm means the flexible
+// space cannot grow (done = 1); S_V0 = 1 / norm normalises it.
+__global__ __launch_bounds__(256) void k_sc_fl_vnorm(double *S, const double *p, int64_t n)
+{
+    __shared__ double red[4];
+    const double v2 = sum_parts(p, n, red);
+    if (threadIdx.x != 0) return;
+    const double t = sqrt(v2);
+    S[S_V0] = 0.0;
+    if (S[S_DONE] != 0.0) return;
+    S[S_FL_TKK] = t;
+    if (!finite(t)) S[S_DONE] = 2.0;
+    else if (t == 0.0) S[S_DONE] = 1.0;
+    else S[S_V0] = 1.0 / t;
+}
+
+// History row of iteration k: [(projected residual, set later), t_kk,
+// M[k+1, k], done, (lambda_k, set later)]; advances the row counter.
+__global__ void k_sc_fl_hist(double *S, const double *M, int k, int ldm, double *hist)
+{
+    if (threadIdx.x != 0) return;
+    const int64_t row = int64_t(S[S_HROW]);
+    if (hist && row < int64_t(S[S_ITER])) {
+        double *h = hist + row * KCT_HIST_COLS;
+        const bool live = int(S[S_KGK]) == k + 1;
+        h[0] = 0.0;
+        h[1] = live ? S[S_FL_TKK] : 0.0;
+        h[2] = live ? M[int64_t(k) * ldm + k + 1] : 0.0;
+        h[3] = S[S_DONE];
+        h[4] = S[S_HLAM];
+    }
+    S[S_HROW] = double(row + 1);
+}
+
+} // namespace
+
+int fl_groups(int64_t n)
+{
+    const int64_t g = (n + 1023) / 1024;
+    return int(std::max<int64_t>(1, std::min<int64_t>(g, 2048)));
+}
+
+#define FL_CHECK(what) return check_hip(hipGetLastError(), what)
+
+kct_status fl_lap(const Plan &p, const float *pv, const float *Lw, float *q, double *parts, hipStream_t st)
+{
+    const Dims d = dims(p);
+    hipLaunchKernelGGL(k_fl_lap, dim3(fl_groups(d.M)), dim3(256), 0, st, pv, Lw, d, q, parts);
+    FL_CHECK("weighted Laplacian");
+}
+
+kct_status fl_cg_update(float *t, float *r, const float *pv, const float *q, int64_t n, const double *S,
+                        double *psum, double *psq, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fl_cg_update, dim3(fl_groups(n)), dim3(256), 0, st, t, r, pv, q, n, S, psum, psq);
+    FL_CHECK("inner CG update");
+}
+
+kct_status fl_cg_dir(float *r, float *pv, int64_t n, const double *S, bool first, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fl_cg_dir, dim3(fl_groups(n)), dim3(256), 0, st, r, pv, n, S, first ? 1 : 0);
+    FL_CHECK("inner CG direction");
+}
+
+kct_status fl_dtl(const Plan &p, const float *v3, const float *Lw, float *out, double *psum, double *psq,
+                  hipStream_t st)
+{
+    const Dims d = dims(p);
+    hipLaunchKernelGGL(k_fl_dtl, dim3(fl_groups(d.M)), dim3(256), 0, st, v3, Lw, d, out, psum, psq);
+    FL_CHECK("weighted divergence");
+}
+
+kct_status fl_sum(const float *v, int64_t n, double *parts, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fl_sum, dim3(fl_groups(n)), dim3(256), 0, st, v, n, parts);
+    FL_CHECK("sum");
+}
+
+kct_status fl_axpy_sum(float *r, const float *g, int64_t n, const double *S, int ci, double *psum, double *psq,
+                       hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fl_axpy_sum, dim3(fl_groups(n)), dim3(256), 0, st, r, g, n, S, ci, psum, psq);
+    FL_CHECK("E^T correction");
+}
+
+kct_status fl_shift(float *out, const float *in, int64_t n, const double *S, int ci, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fl_shift, dim3(fl_groups(n)), dim3(256), 0, st, out, in, n, S, ci);
+    FL_CHECK("E correction");
+}
+
+kct_status fl_fill_s(float *out, int64_t n, const double *S, int ci, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fl_fill_s, dim3(fl_groups(n)), dim3(256), 0, st, out, n, S, ci);
+    FL_CHECK("fill");
+}
+
+kct_status fl_bbar(float *out, const float *b, const float *a, int64_t n, const double *S, double *parts,
+                   hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fl_bbar, dim3(fl_groups(n)), dim3(256), 0, st, out, b, a, n, S, parts);
+    FL_CHECK("bbar");
+}
+
+kct_status fl_combine(float *x, const float *Z, int64_t n, const double *coef, const double *S, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fl_combine, dim3(fl_groups(n)), dim3(256), 0, st, x, Z, n, coef, S);
+    FL_CHECK("flexible combination");
+}
+
+kct_status fl_sc_init(double *S, Reduced ca, Reduced ab, int n_iter, double lam, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sc_fl_init, dim3(1), dim3(256), 0, st, S, ca.ptr, ca.n, ab.ptr, ab.n, n_iter, lam);
+    FL_CHECK("fLSQR init");
+}
+
+kct_status fl_sc_beta1(double *S, Reduced b2, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sc_fl_beta1, dim3(1), dim3(256), 0, st, S, b2.ptr, b2.n);
+    FL_CHECK("fLSQR beta1");
+}
+
+kct_status fl_sc_ecoef(double *S, Reduced dot, int ci, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sc_fl_ecoef, dim3(1), dim3(256), 0, st, S, dot.ptr, dot.n, ci);
+    FL_CHECK("E coefficient");
+}
+
+kct_status fl_sc_cg_init(double *S, Reduced sum, Reduced sq, int64_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sc_fl_cg_init, dim3(1), dim3(256), 0, st, S, sum.ptr, sum.n, sq.ptr, sq.n, n);
+    FL_CHECK("inner CG init");
+}
+
+kct_status fl_sc_cg_alpha(double *S, Reduced pq, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sc_fl_cg_alpha, dim3(1), dim3(256), 0, st, S, pq.ptr, pq.n);
+    FL_CHECK("inner CG alpha");
+}
+
+kct_status fl_sc_cg_beta(double *S, Reduced sum, Reduced sq, int64_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sc_fl_cg_beta, dim3(1), dim3(256), 0, st, S, sum.ptr, sum.n, sq.ptr, sq.n, n);
+    FL_CHECK("inner CG beta");
+}
+
+kct_status fl_sc_vnorm(double *S, Reduced v2, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sc_fl_vnorm, dim3(1), dim3(256), 0, st, S, v2.ptr, v2.n);
+    FL_CHECK("fLSQR vector norm");
+}
+
+kct_status fl_sc_hist(double *S, const double *M, int k, int ldm, double *hist, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sc_fl_hist, dim3(1), dim3(64), 0, st, S, M, k, ldm, hist);
+    FL_CHECK("fLSQR history");
+}
+
+} // namespace kct

@@ -46,6 +46,10 @@ kct_status sk_lsmr_alpha(double *S, Reduced v, double *hist, hipStream_t st);
 kct_status sk_hybrid_solve(double *S, const double *gk, double *work, double *coef, hipStream_t st);
 kct_status sk_hybrid_choose(double *S, const double *gk, double *work, double *coef, double *hist, int rule,
                             double noise_level, hipStream_t st);
+// The same on a dense (k+1) x k matrix M (column-major, leading dimension ldm,
+// rows 0..j+1 of column j used), beta_1 = S[S_BETA], coef = y.
+kct_status sk_hybrid_choose_dense(double *S, const double *M, int ldm, double *work, double *coef, double *hist,
+                                  int rule, double noise_level, hipStream_t st);
 
 // Total variation (IRN-TV).
 int tv_num_groups(int64_t M);

@@ -502,19 +502,22 @@ __global__ __launch_bounds__(256) void k_sc_explicit(double *S, const double *p,
 
 // ---------------------------------------------------------------------------
 // Hybrid LSQR with lambda_k chosen at every iteration (GCV or discrepancy
-// principle on the projected problem).  One workgroup:
-//   1. B_k ((k+1) x k lower bidiagonal from the stored alpha, beta) is
-//      copied to W, and Q = I;
+// principle on the projected problem), and the projected solve of hybrid
+// fLSQR-TV.  One workgroup:
+//   1. B_k ((k+1) x k: lower bidiagonal from the stored alpha, beta, or the
+//      upper Hessenberg M_k of the flexible process) is copied to W, and Q = I;
 //   2. one-sided Jacobi: pairs of columns of W are rotated until they are
 //      orthogonal (round-robin pair order, k/2 pairs per round, one thread per
 //      pair), the same rotations accumulate in Q; then sigma_i = ||W_i||,
 //      P_i = W_i / sigma_i, B_k = P diag(sigma) Q^T;
-//   3. c_i = beta_1 P_i[0] for i < k, and c_k = beta_1 / ||n|| with n the null
-//      vector of B_k^T (n_0 = 1, n_{j+1} = -alpha_{j+1} n_j / beta_{j+2}): the
-//      part of beta_1 e_1 outside the range of B_k;
+//   3. c_i = beta_1 P_i[0] for i < k, and c_k = beta_1 n_0 / ||n|| with n the
+//      null vector of B_k^T (n_0 = 1, n_{j+1} = -sum_{i<=j} n_i B[i, j] /
+//      B[j+1, j], for the bidiagonal -alpha_{j+1} n_j / beta_{j+2}): the part
+//      of beta_1 e_1 outside the range of B_k;
 //   4. lambda_k by the rule (the same search as the oracle's);
-//   5. y = Q diag(sigma / (sigma^2 + lambda^2)) c, coef_i = y_i / alpha_i, and
-//      history row k gets the projected Tikhonov residual and lambda_k.
+//   5. y = Q diag(sigma / (sigma^2 + lambda^2)) c; coef_i = y_i / alpha_i for
+//      the unnormalised GK basis, y_i for fLSQR-TV; history row k gets the
+//      projected Tikhonov residual and lambda_k.
 // ---------------------------------------------------------------------------
 namespace hyb {
 
@@ -548,8 +551,11 @@ __device__ inline double gcv(const double *sig, const double *c, int k, double l
 
 } // namespace hyb
 
-__global__ __launch_bounds__(256) void k_hybrid_choose(double *S, const double *gk, double *work, double *coef,
-                                                       double *hist, int rule, double noise_level)
+// DENSE: src is M_k column-major with leading dimension ldm and beta_1 is
+// S[S_BETA]; otherwise src is the interleaved [beta_1, alpha_1, beta_2, ...].
+template <bool DENSE>
+__device__ void hybrid_choose_body(double *S, const double *src, int ldm, double *work, double *coef, double *hist,
+                                   int rule, double noise_level)
 {
     using namespace hyb;
     __shared__ int rotated;
@@ -565,14 +571,22 @@ __global__ __launch_bounds__(256) void k_hybrid_choose(double *S, const double *
     double *sig = Q + k * k;  // k
     double *c = sig + k;      // k + 1
     double *y = c + k + 1;    // k
-    const double beta1 = gk[0];
+    const double beta1 = DENSE ? S[S_BETA] : src[0];
 
-    for (int e = tid; e < m * k; e += 256) W[e] = 0.0;
     for (int e = tid; e < k * k; e += 256) Q[e] = (e % (k + 1) == 0) ? 1.0 : 0.0;
-    __syncthreads();
-    for (int j = tid; j < k; j += 256) {
-        W[j * m + j] = gk[2 * j + 1];     // alpha_{j+1}
-        W[j * m + j + 1] = gk[2 * j + 2]; // beta_{j+2}
+    if constexpr (DENSE) {
+        for (int e = tid; e < m * k; e += 256) {
+            const int j = e / m, i = e - j * m;
+            W[e] = i <= j + 1 ? src[int64_t(j) * ldm + i] : 0.0;
+        }
+        __syncthreads();
+    } else {
+        for (int e = tid; e < m * k; e += 256) W[e] = 0.0;
+        __syncthreads();
+        for (int j = tid; j < k; j += 256) {
+            W[j * m + j] = src[2 * j + 1];     // alpha_{j+1}
+            W[j * m + j + 1] = src[2 * j + 2]; // beta_{j+2}
+        }
     }
     __syncthreads();
 
@@ -641,23 +655,46 @@ __global__ __launch_bounds__(256) void k_hybrid_choose(double *S, const double *
     }
     if (tid == 0) {
         // c_k from the null vector of B_k^T, rescaled to stay in range.
-        double n0 = 1.0, cur = 1.0, ssq = 1.0;
-        bool zero = false;
-        for (int j = 0; j < k && !zero; ++j) {
-            const double al = gk[2 * j + 1], be = gk[2 * j + 2];
-            if (be == 0.0) {
-                zero = true;
-                break;
+        if constexpr (DENSE) {
+            double *nv = y + k; // k + 1 entries
+            double ssq = 1.0;
+            bool zero = false;
+            nv[0] = 1.0;
+            for (int j = 0; j < k; ++j) {
+                const double *col = src + int64_t(j) * ldm;
+                if (col[j + 1] == 0.0) {
+                    zero = true;
+                    break;
+                }
+                double t = 0.0;
+                for (int i = 0; i <= j; ++i) t += nv[i] * col[i];
+                nv[j + 1] = -t / col[j + 1];
+                ssq += nv[j + 1] * nv[j + 1];
+                if (fabs(nv[j + 1]) > 1e100) {
+                    for (int i = 0; i <= j + 1; ++i) nv[i] *= 1e-100;
+                    ssq *= 1e-200;
+                }
             }
-            cur = -al * cur / be;
-            ssq += cur * cur;
-            if (fabs(cur) > 1e100) {
-                cur *= 1e-100;
-                ssq *= 1e-200;
-                n0 *= 1e-100;
+            c[k] = zero ? 0.0 : beta1 * nv[0] / sqrt(ssq);
+        } else {
+            double n0 = 1.0, cur = 1.0, ssq = 1.0;
+            bool zero = false;
+            for (int j = 0; j < k && !zero; ++j) {
+                const double al = src[2 * j + 1], be = src[2 * j + 2];
+                if (be == 0.0) {
+                    zero = true;
+                    break;
+                }
+                cur = -al * cur / be;
+                ssq += cur * cur;
+                if (fabs(cur) > 1e100) {
+                    cur *= 1e-100;
+                    ssq *= 1e-200;
+                    n0 *= 1e-100;
+                }
             }
+            c[k] = zero ? 0.0 : beta1 * n0 / sqrt(ssq);
         }
-        c[k] = zero ? 0.0 : beta1 * n0 / sqrt(ssq);
     }
     __syncthreads();
     if (tid == 0) {
@@ -741,7 +778,7 @@ __global__ __launch_bounds__(256) void k_hybrid_choose(double *S, const double *
                 v += Q[i * k + r] * (gi * c[i]);
             }
         y[r] = v;
-        coef[r] = v / gk[2 * r + 1];
+        coef[r] = DENSE ? v : v / src[2 * r + 1];
     }
     __syncthreads();
     if (tid == 0) {
@@ -760,6 +797,18 @@ __global__ __launch_bounds__(256) void k_hybrid_choose(double *S, const double *
             }
         }
     }
+}
+
+__global__ __launch_bounds__(256) void k_hybrid_choose(double *S, const double *gk, double *work, double *coef,
+                                                       double *hist, int rule, double noise_level)
+{
+    hybrid_choose_body<false>(S, gk, 0, work, coef, hist, rule, noise_level);
+}
+
+__global__ __launch_bounds__(256) void k_hybrid_choose_dense(double *S, const double *M, int ldm, double *work,
+                                                             double *coef, double *hist, int rule, double noise_level)
+{
+    hybrid_choose_body<true>(S, M, ldm, work, coef, hist, rule, noise_level);
 }
 
 int vec_groups(int64_t n)
@@ -924,6 +973,12 @@ kct_status sk_hybrid_choose(double *S, const double *gk, double *work, double *c
 {
     SC1(k_hybrid_choose, dim3(1), dim3(256), 0, st, S, gk, work, coef, hist, rule, noise_level);
     return check_hip(hipGetLastError(), "hybrid parameter choice");
+}
+kct_status sk_hybrid_choose_dense(double *S, const double *M, int ldm, double *work, double *coef, double *hist,
+                                  int rule, double noise_level, hipStream_t st)
+{
+    SC1(k_hybrid_choose_dense, dim3(1), dim3(256), 0, st, S, M, ldm, work, coef, hist, rule, noise_level);
+    return check_hip(hipGetLastError(), "projected Tikhonov solve");
 }
 
 } // namespace kct

@@ -27,7 +27,13 @@
 //           r_s *= W; v = A_s^T r_s; x += lam V_s v.  The angles are
 //           permuted once so that every subset is a contiguous block, and the
 //           projectors run on a view of the plan holding that block.
+//   fLSQR-TV (Sec. 2.3.2) weights L from x (L = I at k = 0); r = A^T u_k;
+//           r = E^T r; t = K^+ r (inner CG); V_k = L D t, orthonormalised
+//           against V_1..V_{k-1}; r = D^T L V_k; t = K^+ r; Z_k = E t;
+//           u_{k+1} = A Z_k orthonormalised against u_1..u_k (column k of
+//           M); projected Tikhonov solve of (M_k, beta1 e1); x = x0 + Z_k y.
 
+#include "flsqr.hpp"
 #include "gmres.hpp"
 #include "krylov.hpp"
 #include "sart.hpp"
@@ -51,7 +57,7 @@ struct Layout {
     int64_t nparts = 0;
 };
 
-bool solver_ok(int s) { return s >= KCT_CGLS && s <= KCT_OS_SART; }
+bool solver_ok(int s) { return s >= KCT_CGLS && s <= KCT_HYBRID_FLSQR_TV; }
 
 bool is_sart(int s) { return s == KCT_SIRT || s == KCT_OS_SART; }
 
@@ -65,6 +71,13 @@ kct_status check_params(const kct_solve_params *prm)
         if (prm->tv_outer < 1 || prm->tv_inner < 1 || int64_t(prm->tv_outer) * prm->tv_inner > 100000)
             return fail(KCT_E_INVALID_ARG, "IRN-TV needs tv_outer >= 1 and tv_inner >= 1");
         if (!(prm->tv_eps > 0.0) || !std::isfinite(prm->tv_eps)) return fail(KCT_E_INVALID_ARG, "tv_eps must be > 0");
+    }
+    if (prm->solver == KCT_HYBRID_FLSQR_TV) {
+        if (prm->tv_inner < 1 || prm->tv_inner > 10000)
+            return fail(KCT_E_INVALID_ARG, "fLSQR-TV needs tv_inner >= 1 CG steps per pseudoinverse");
+        if (prm->tv_outer != 0) return fail(KCT_E_INVALID_ARG, "fLSQR-TV takes no tv_outer (n_iter iterations)");
+        if (!(prm->tv_eps > 0.0) || !std::isfinite(prm->tv_eps)) return fail(KCT_E_INVALID_ARG, "tv_eps must be > 0");
+        if (prm->vec_dtype != KCT_F32) return fail(KCT_E_DTYPE, "fLSQR-TV stores its vectors in FP32");
     }
     if (prm->n_iter < 0 || prm->n_iter > 100000) return fail(KCT_E_INVALID_ARG, "n_iter out of range");
     if (!(prm->lambda >= 0.0) || !std::isfinite(prm->lambda)) return fail(KCT_E_INVALID_ARG, "lambda must be >= 0");
@@ -98,8 +111,8 @@ kct_status check_params(const kct_solve_params *prm)
     if (prm->lambda_rule != KCT_LAMBDA_FIXED) {
         if (prm->lambda_rule != KCT_LAMBDA_GCV && prm->lambda_rule != KCT_LAMBDA_DP)
             return fail(KCT_E_INVALID_ARG, "unknown lambda rule");
-        if (prm->solver != KCT_HYBRID_LSQR)
-            return fail(KCT_E_INVALID_ARG, "only hybrid LSQR chooses lambda during the iterations");
+        if (prm->solver != KCT_HYBRID_LSQR && prm->solver != KCT_HYBRID_FLSQR_TV)
+            return fail(KCT_E_INVALID_ARG, "only hybrid LSQR and fLSQR-TV choose lambda during the iterations");
         if (prm->lambda_rule == KCT_LAMBDA_DP && !(prm->noise_level > 0.0 && std::isfinite(prm->noise_level)))
             return fail(KCT_E_INVALID_ARG, "the discrepancy principle needs a noise level > 0");
     }
@@ -179,6 +192,19 @@ Layout layout(const Plan &p, const kct_solve_params &prm)
             L.v[4] = o; o += up(size_t(N) * 4);          // b in the permuted angle order
             L.work = o; o += up(sizeof(AngleGeo) * size_t(p.gp.na));
         }
+        break;
+    }
+    case KCT_HYBRID_FLSQR_TV: {
+        const size_t kk = size_t(std::max(k, 1));
+        L.v[0] = o; o += up(size_t(N) * 4 * std::max<size_t>(k + 1, 2)); // u_1..u_{k+1} (u_2 holds A 1 at first)
+        L.v[1] = o; o += up(size_t(M) * 4 * 3 * kk);                     // V_1..V_k, gradient space
+        L.v[2] = o; o += up(size_t(M) * 4 * kk);                         // Z_1..Z_k
+        L.v[3] = o; o += up(size_t(M) * 4);                              // g = A^T A 1
+        L.v[4] = o; o += up(size_t(M) * 4 * 4);                          // inner CG t, r, p, q
+        L.v[5] = o; o += up(size_t(M) * 4);                              // L weights
+        L.gk = o; o += up(sizeof(double) * (kk + 1) * kk * 2);           // M ((k+1) x k), T (k x k)
+        L.work = o; o += up(sizeof(double) * ((2 * kk + 1) * (kk + 1) + 5 * kk + 10));
+        L.coef = o; o += up(sizeof(double) * (kk + 1));
         break;
     }
     case KCT_IRN_TV_CGLS:
@@ -600,6 +626,116 @@ kct_status sa_iter(kct_state &s)
     return KCT_OK;
 }
 
+// ---------------------------------------------------------------- fLSQR-TV
+int fl_K(const kct_state &s) { return std::max(s.prm.n_iter, 1); }
+int fl_ldm(const kct_state &s) { return s.prm.n_iter + 1; }
+float *fl_U(kct_state &s, int i) { return static_cast<float *>(s.v(0)) + size_t(i) * size_t(s.N()); }
+float *fl_V(kct_state &s, int i) { return static_cast<float *>(s.v(1)) + size_t(i) * 3 * size_t(s.M()); }
+float *fl_Z(kct_state &s, int i) { return static_cast<float *>(s.v(2)) + size_t(i) * size_t(s.M()); }
+float *fl_g(kct_state &s) { return static_cast<float *>(s.v(3)); }
+float *fl_tmp(kct_state &s, int i) { return static_cast<float *>(s.v(4)) + size_t(i) * size_t(s.M()); }
+float *fl_w(kct_state &s) { return static_cast<float *>(s.v(5)); }
+double *fl_Mat(kct_state &s) { return reinterpret_cast<double *>(s.ws + s.L.gk); }
+double *fl_T(kct_state &s) { return fl_Mat(s) + size_t(fl_ldm(s)) * size_t(fl_K(s)); }
+
+kct_status fl_init(kct_state &s)
+{
+    Plan &p = *s.plan;
+    const int64_t N = s.N(), M = s.M();
+    float *a = fl_U(s, 1); // A 1, until the first iteration writes u_2
+    KCT_TRY(vk_fill(fl_tmp(s, 0), KCT_F32, M, 1.f, s.st));
+    Epilogue ef;
+    ef.partials = s.pa();
+    KCT_TRY(forward_into(s, fl_tmp(s, 0), a, ef)); // a = A 1 -> ||a||^2
+    const Reduced rca = red(s, s.pa(), fwd_num_groups(p), 0);
+    KCT_TRY(gm_dot(a, s.b, KCT_F32, N, s.pb(), s.st)); // a^T b
+    KCT_TRY(fl_sc_init(s.S(), rca, red(s, s.pb(), gm_num_groups(N), 1), s.prm.n_iter, s.prm.lambda, s.st));
+    KCT_TRY(fl_fill_s(s.x, M, s.S(), S_FL_C0, s.st)); // x = x0
+    Epilogue eb;
+    KCT_TRY(launch_backward(p, a, KCT_F32, fl_g(s), KCT_F32, eb, s.st)); // g = A^T a
+    KCT_TRY(fl_bbar(fl_U(s, 0), s.b, a, N, s.S(), s.pa(), s.st));        // bbar = b - c0 a -> ||bbar||^2
+    KCT_TRY(fl_sc_beta1(s.S(), red(s, s.pa(), fl_groups(N), 0), s.st));
+    return gm_scale(fl_U(s, 0), KCT_F32, N, s.S(), S_V0, s.st);
+}
+
+// t = K^+ r by tv_inner CG steps; the sums of r's entries and squares are in
+// pa and pb (nparts each) from the kernel that produced r.
+kct_status fl_cg(kct_state &s, int64_t nparts)
+{
+    Plan &p = *s.plan;
+    const int64_t M = s.M();
+    float *t = fl_tmp(s, 0), *r = fl_tmp(s, 1), *pv = fl_tmp(s, 2), *q = fl_tmp(s, 3);
+    const int ng = fl_groups(M);
+    KCT_TRY(fl_sc_cg_init(s.S(), red(s, s.pa(), nparts, 0), red(s, s.pb(), nparts, 1), M, s.st));
+    KCT_TRY(vk_fill(t, KCT_F32, M, 0.f, s.st));
+    KCT_TRY(fl_cg_dir(r, pv, M, s.S(), true, s.st));
+    for (int it = 0; it < s.prm.tv_inner; ++it) {
+        KCT_TRY(fl_lap(p, pv, fl_w(s), q, s.pa(), s.st));
+        KCT_TRY(fl_sc_cg_alpha(s.S(), red(s, s.pa(), ng, 0), s.st));
+        KCT_TRY(fl_cg_update(t, r, pv, q, M, s.S(), s.pa(), s.pb(), s.st));
+        if (it + 1 == s.prm.tv_inner) break;
+        KCT_TRY(fl_sc_cg_beta(s.S(), red(s, s.pa(), ng, 0), red(s, s.pb(), ng, 1), M, s.st));
+        KCT_TRY(fl_cg_dir(r, pv, M, s.S(), false, s.st));
+    }
+    return KCT_OK;
+}
+
+kct_status fl_iter(kct_state &s)
+{
+    Plan &p = *s.plan;
+    const int k = s.enqueued, ldm = fl_ldm(s);
+    const int64_t N = s.N(), M = s.M(), M3 = 3 * M;
+    float *t = fl_tmp(s, 0), *r = fl_tmp(s, 1);
+    if (k == 0) KCT_TRY(vk_fill(fl_w(s), KCT_F32, M, 1.f, s.st)); // L = I
+    else KCT_TRY(tv_weights(p, s.x, fl_w(s), s.prm.tv_eps, s.st));
+    // v = P^T A^T u_k = L D K^+ E^T A^T u_k.
+    Epilogue eb;
+    KCT_TRY(launch_backward(p, fl_U(s, k), KCT_F32, r, KCT_F32, eb, s.st));
+    KCT_TRY(fl_sum(r, M, s.pa(), s.st));
+    KCT_TRY(fl_sc_ecoef(s.S(), red(s, s.pa(), fl_groups(M), 0), S_FL_E, s.st));
+    KCT_TRY(fl_axpy_sum(r, fl_g(s), M, s.S(), S_FL_E, s.pa(), s.pb(), s.st));
+    KCT_TRY(fl_cg(s, fl_groups(M)));
+    float *Vk = fl_V(s, k);
+    KCT_TRY(tv_grad_store(p, t, KCT_F32, fl_w(s), Vk, nullptr, -1, 1.0, false, s.st));
+    for (int i = 0; i < k; ++i) { // modified Gram-Schmidt against v_1..v_{k-1}
+        KCT_TRY(gm_dot(Vk, fl_V(s, i), KCT_F32, M3, s.pa(), s.st));
+        const Reduced h = red(s, s.pa(), gm_num_groups(M3), 0);
+        KCT_TRY(gm_sc_h(s.S(), h.ptr, h.n, fl_T(s), i, k, fl_K(s), s.st));
+        KCT_TRY(gm_axpy(Vk, fl_V(s, i), KCT_F32, M3, s.S(), S_P0, s.st));
+    }
+    KCT_TRY(gm_dot(Vk, Vk, KCT_F32, M3, s.pa(), s.st));
+    KCT_TRY(fl_sc_vnorm(s.S(), red(s, s.pa(), gm_num_groups(M3), 0), s.st));
+    KCT_TRY(gm_scale(Vk, KCT_F32, M3, s.S(), S_V0, s.st));
+    // z_k = P v_k = E K^+ D^T L v_k.
+    KCT_TRY(fl_dtl(p, Vk, fl_w(s), r, s.pa(), s.pb(), s.st));
+    KCT_TRY(fl_cg(s, fl_groups(M)));
+    KCT_TRY(gm_dot(fl_g(s), t, KCT_F32, M, s.pa(), s.st));
+    KCT_TRY(fl_sc_ecoef(s.S(), red(s, s.pa(), gm_num_groups(M), 0), S_FL_E, s.st));
+    float *Zk = fl_Z(s, k);
+    KCT_TRY(fl_shift(Zk, t, M, s.S(), S_FL_E, s.st));
+    // u_{k+1}: A z_k orthonormalised against u_1..u_k, coefficients in column k of M.
+    float *U1 = fl_U(s, k + 1);
+    Epilogue ef;
+    KCT_TRY(forward_into(s, Zk, U1, ef));
+    for (int i = 0; i <= k; ++i) {
+        KCT_TRY(gm_dot(U1, fl_U(s, i), KCT_F32, N, s.pa(), s.st));
+        const Reduced h = red(s, s.pa(), gm_num_groups(N), 0);
+        KCT_TRY(gm_sc_h(s.S(), h.ptr, h.n, fl_Mat(s), i, k, ldm, s.st));
+        KCT_TRY(gm_axpy(U1, fl_U(s, i), KCT_F32, N, s.S(), S_P0, s.st));
+    }
+    KCT_TRY(gm_dot(U1, U1, KCT_F32, N, s.pa(), s.st));
+    const Reduced u2 = red(s, s.pa(), gm_num_groups(N), 0);
+    KCT_TRY(gm_sc_norm(s.S(), u2.ptr, u2.n, fl_Mat(s), k, ldm, s.st));
+    KCT_TRY(gm_scale(U1, KCT_F32, N, s.S(), S_V0, s.st));
+    // Projected Tikhonov solve with lambda_k, then x = x0 + Z_k y.
+    double *work = reinterpret_cast<double *>(s.ws + s.L.work);
+    double *coef = reinterpret_cast<double *>(s.ws + s.L.coef);
+    KCT_TRY(fl_sc_hist(s.S(), fl_Mat(s), k, ldm, s.hist, s.st));
+    KCT_TRY(sk_hybrid_choose_dense(s.S(), fl_Mat(s), ldm, work, coef, s.hist, s.prm.lambda_rule,
+                                   s.prm.noise_level, s.st));
+    return fl_combine(s.x, fl_Z(s, 0), M, coef, s.S(), s.st);
+}
+
 kct_status enqueue_init(kct_state &s)
 {
     switch (s.prm.solver) {
@@ -612,6 +748,7 @@ kct_status enqueue_init(kct_state &s)
     case KCT_BA_GMRES: return gm_init(s);
     case KCT_SIRT:
     case KCT_OS_SART: return sa_init(s);
+    case KCT_HYBRID_FLSQR_TV: return fl_init(s);
     }
     return fail(KCT_E_INVALID_ARG, "unknown solver");
 }
@@ -649,6 +786,7 @@ kct_status solver_iter(kct_state &s)
     case KCT_BA_GMRES: return gm_iter(s);
     case KCT_SIRT:
     case KCT_OS_SART: return sa_iter(s);
+    case KCT_HYBRID_FLSQR_TV: return fl_iter(s);
     }
     return fail(KCT_E_INVALID_ARG, "unknown solver");
 }

@@ -45,6 +45,7 @@ def test_header_constants_match_binding():
     assert int(vals["KCT_AB_GMRES"]) == _lib.KCT_AB_GMRES and int(vals["KCT_BA_GMRES"]) == _lib.KCT_BA_GMRES
     assert int(vals["KCT_BP_MATCHED"]) == _lib.KCT_BP_MATCHED and int(vals["KCT_BP_INTERP"]) == _lib.KCT_BP_INTERP
     assert int(vals["KCT_SIRT"]) == _lib.KCT_SIRT and int(vals["KCT_OS_SART"]) == _lib.KCT_OS_SART
+    assert int(vals["KCT_HYBRID_FLSQR_TV"]) == _lib.KCT_HYBRID_FLSQR_TV
     assert int(re.search(r"#define KCT_HIST_COLS (\d+)", src).group(1)) == _lib.KCT_HIST_COLS
     for name, code in _lib.STATUS_NAMES.items():
         assert int(vals[code]) == name
