@@ -11,9 +11,9 @@
 // direction update), so rounding cannot drive the iterate along the null
 // space.  D is the forward difference with a zero last difference per axis,
 // as in IRN-TV.  Volumes are x-fastest; gradient-space vectors are planar
-// (component c of voxel e at c*M + e).  All vector kernels are one thread per
-// voxel in a grid-stride loop and bound by HBM bandwidth; the stencil reads
-// of the six neighbours come from L2.
+// (component c of voxel e at c*M + e).  The vector kernels are one thread per
+// voxel in a grid-stride loop, the stencils one workgroup per x-row; all are
+// bound by HBM bandwidth, with the six neighbours' reads served by L2.
 
 #include "flsqr.hpp"
 
@@ -53,34 +53,42 @@ __device__ inline bool finite(double v) { return v == v && v - v == 0.0; }
 
 #define FL_LOOP(e, n) for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < (n); e += int64_t(gridDim.x) * 256)
 
+// The stencil kernels walk x-rows: workgroups stride over the ny*nz rows and
+// the threads over x, so the voxel coordinates cost one division per row
+// instead of a 64-bit division and modulo per voxel.
+
 __global__ __launch_bounds__(256) void k_fl_lap(const float *__restrict__ p, const float *__restrict__ Lw, Dims d,
                                                 float *__restrict__ q, double *parts)
 {
     __shared__ double red[4];
     const int64_t sxy = int64_t(d.nx) * d.ny;
+    const int64_t rows = int64_t(d.ny) * d.nz;
     double acc = 0.0;
-    FL_LOOP(e, d.M)
-    {
-        const int i = int(e % d.nx), j = int((e / d.nx) % d.ny), k = int(e / sxy);
-        const float c = p[e], le = Lw[e], we = le * le;
-        float t = 0.f;
-        if (i < d.nx - 1) t -= we * (p[e + 1] - c);
-        if (i > 0) {
-            const float l = Lw[e - 1];
-            t += l * l * (c - p[e - 1]);
+    for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+        const int j = int(row % d.ny), k = int(row / d.ny);
+        const int64_t e0 = row * d.nx;
+        for (int i = threadIdx.x; i < d.nx; i += 256) {
+            const int64_t e = e0 + i;
+            const float c = p[e], le = Lw[e], we = le * le;
+            float t = 0.f;
+            if (i < d.nx - 1) t -= we * (p[e + 1] - c);
+            if (i > 0) {
+                const float l = Lw[e - 1];
+                t += l * l * (c - p[e - 1]);
+            }
+            if (j < d.ny - 1) t -= we * (p[e + d.nx] - c);
+            if (j > 0) {
+                const float l = Lw[e - d.nx];
+                t += l * l * (c - p[e - d.nx]);
+            }
+            if (k < d.nz - 1) t -= we * (p[e + sxy] - c);
+            if (k > 0) {
+                const float l = Lw[e - sxy];
+                t += l * l * (c - p[e - sxy]);
+            }
+            q[e] = t;
+            acc += double(c) * double(t);
         }
-        if (j < d.ny - 1) t -= we * (p[e + d.nx] - c);
-        if (j > 0) {
-            const float l = Lw[e - d.nx];
-            t += l * l * (c - p[e - d.nx]);
-        }
-        if (k < d.nz - 1) t -= we * (p[e + sxy] - c);
-        if (k > 0) {
-            const float l = Lw[e - sxy];
-            t += l * l * (c - p[e - sxy]);
-        }
-        q[e] = t;
-        acc += double(c) * double(t);
     }
     acc = block_sum(acc, red);
     if (threadIdx.x == 0) parts[blockIdx.x] = acc;
@@ -126,21 +134,25 @@ __global__ __launch_bounds__(256) void k_fl_dtl(const float *__restrict__ v3, co
 {
     __shared__ double red[4];
     const int64_t sxy = int64_t(d.nx) * d.ny;
+    const int64_t rows = int64_t(d.ny) * d.nz;
     double s1 = 0.0, s2 = 0.0;
-    FL_LOOP(e, d.M)
-    {
-        const int i = int(e % d.nx), j = int((e / d.nx) % d.ny), k = int(e / sxy);
-        const float le = Lw[e];
-        float t = 0.f;
-        if (i < d.nx - 1) t -= le * v3[e];
-        if (i > 0) t += Lw[e - 1] * v3[e - 1];
-        if (j < d.ny - 1) t -= le * v3[d.M + e];
-        if (j > 0) t += Lw[e - d.nx] * v3[d.M + e - d.nx];
-        if (k < d.nz - 1) t -= le * v3[2 * d.M + e];
-        if (k > 0) t += Lw[e - sxy] * v3[2 * d.M + e - sxy];
-        out[e] = t;
-        s1 += t;
-        s2 += double(t) * t;
+    for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+        const int j = int(row % d.ny), k = int(row / d.ny);
+        const int64_t e0 = row * d.nx;
+        for (int i = threadIdx.x; i < d.nx; i += 256) {
+            const int64_t e = e0 + i;
+            const float le = Lw[e];
+            float t = 0.f;
+            if (i < d.nx - 1) t -= le * v3[e];
+            if (i > 0) t += Lw[e - 1] * v3[e - 1];
+            if (j < d.ny - 1) t -= le * v3[d.M + e];
+            if (j > 0) t += Lw[e - d.nx] * v3[d.M + e - d.nx];
+            if (k < d.nz - 1) t -= le * v3[2 * d.M + e];
+            if (k > 0) t += Lw[e - sxy] * v3[2 * d.M + e - sxy];
+            out[e] = t;
+            s1 += t;
+            s2 += double(t) * t;
+        }
     }
     s1 = block_sum(s1, red);
     s2 = block_sum(s2, red);

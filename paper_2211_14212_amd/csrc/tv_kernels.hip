@@ -8,9 +8,9 @@
 // applied to all three gradient components of that voxel.  The gradient-space
 // residual r2 is stored planar: component c of voxel e at r2[c*M + e].
 //
-// All kernels are one thread per voxel in a grid-stride loop (neighbour reads
-// along x are contiguous, along y and z one row or slice away, all coalesced
-// across a wave) and bound by HBM bandwidth.
+// All kernels are one thread per voxel, one workgroup per x-row at a time
+// (neighbour reads along x are contiguous, along y and z one row or slice
+// away, all coalesced across a wave), and bound by HBM bandwidth.
 
 #include "krylov.hpp"
 
@@ -34,11 +34,16 @@ struct Dims {
     int64_t M;
 };
 
+// The kernels walk x-rows: workgroups stride over the ny*nz rows and the
+// threads over x, so voxel (i, j, k) costs one division per row instead of a
+// 64-bit division and modulo per voxel.
+#define TV_ROWS(d)                                                                                                 \
+    for (int64_t row = blockIdx.x, rows = int64_t(d.ny) * d.nz; row < rows; row += gridDim.x)
+
 template <typename T>
-__device__ inline void grad_at(const T *x, Dims d, int64_t e, float &gx, float &gy, float &gz)
+__device__ inline void grad_at(const T *x, Dims d, int64_t e, int i, int j, int k, float &gx, float &gy, float &gz)
 {
     const int64_t sxy = int64_t(d.nx) * d.ny;
-    const int i = int(e % d.nx), j = int((e / d.nx) % d.ny), k = int(e / sxy);
     const float c = to_f32(x[e]);
     gx = i < d.nx - 1 ? to_f32(x[e + 1]) - c : 0.f;
     gy = j < d.ny - 1 ? to_f32(x[e + d.nx]) - c : 0.f;
@@ -49,11 +54,16 @@ __device__ inline void grad_at(const T *x, Dims d, int64_t e, float &gx, float &
 __global__ __launch_bounds__(256) void k_tv_weights(const float *__restrict__ x, float *__restrict__ Lw, Dims d,
                                                     double eps)
 {
-    for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < d.M; e += int64_t(gridDim.x) * 256) {
-        float gx, gy, gz;
-        grad_at(x, d, e, gx, gy, gz);
-        const double w = sqrt(double(gx) * gx + double(gy) * gy + double(gz) * gz + eps * eps);
-        Lw[e] = float(1.0 / sqrt(w));
+    TV_ROWS(d)
+    {
+        const int j = int(row % d.ny), k = int(row / d.ny);
+        for (int i = threadIdx.x; i < d.nx; i += 256) {
+            const int64_t e = row * d.nx + i;
+            float gx, gy, gz;
+            grad_at(x, d, e, i, j, k, gx, gy, gz);
+            const double w = sqrt(double(gx) * gx + double(gy) * gy + double(gz) * gz + eps * eps);
+            Lw[e] = float(1.0 / sqrt(w));
+        }
     }
 }
 
@@ -64,11 +74,16 @@ __global__ __launch_bounds__(256) void k_tv_grad_norm(const T *__restrict__ p, c
 {
     double s = 0.0;
     if (S[S_DONE] == 0.0) {
-        for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < d.M; e += int64_t(gridDim.x) * 256) {
-            float gx, gy, gz;
-            grad_at(p, d, e, gx, gy, gz);
-            const double l = lam * double(Lw[e]);
-            s += l * l * (double(gx) * gx + double(gy) * gy + double(gz) * gz);
+        TV_ROWS(d)
+        {
+            const int j = int(row % d.ny), k = int(row / d.ny);
+            for (int i = threadIdx.x; i < d.nx; i += 256) {
+                const int64_t e = row * d.nx + i;
+                float gx, gy, gz;
+                grad_at(p, d, e, i, j, k, gx, gy, gz);
+                const double l = lam * double(Lw[e]);
+                s += l * l * (double(gx) * gx + double(gy) * gy + double(gz) * gz);
+            }
         }
     }
     s = block_sum_tv(s);
@@ -83,18 +98,23 @@ __global__ __launch_bounds__(256) void k_tv_grad_store(const T *__restrict__ v, 
 {
     const double c = ci >= 0 ? S[ci] : cgiven;
     if (accumulate && c == 0.0) return;
-    for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < d.M; e += int64_t(gridDim.x) * 256) {
-        float gx, gy, gz;
-        grad_at(v, d, e, gx, gy, gz);
-        const double l = c * double(Lw[e]);
-        if (accumulate) {
-            r2[e] = float(double(r2[e]) + l * gx);
-            r2[d.M + e] = float(double(r2[d.M + e]) + l * gy);
-            r2[2 * d.M + e] = float(double(r2[2 * d.M + e]) + l * gz);
-        } else {
-            r2[e] = float(l * gx);
-            r2[d.M + e] = float(l * gy);
-            r2[2 * d.M + e] = float(l * gz);
+    TV_ROWS(d)
+    {
+        const int j = int(row % d.ny), k = int(row / d.ny);
+        for (int i = threadIdx.x; i < d.nx; i += 256) {
+            const int64_t e = row * d.nx + i;
+            float gx, gy, gz;
+            grad_at(v, d, e, i, j, k, gx, gy, gz);
+            const double l = c * double(Lw[e]);
+            if (accumulate) {
+                r2[e] = float(double(r2[e]) + l * gx);
+                r2[d.M + e] = float(double(r2[d.M + e]) + l * gy);
+                r2[2 * d.M + e] = float(double(r2[2 * d.M + e]) + l * gz);
+            } else {
+                r2[e] = float(l * gx);
+                r2[d.M + e] = float(l * gy);
+                r2[2 * d.M + e] = float(l * gz);
+            }
         }
     }
 }
@@ -109,20 +129,24 @@ __global__ __launch_bounds__(256) void k_tv_adjoint_add(T *__restrict__ s, const
     const bool skip = S && S[S_DONE] != 0.0;
     const int64_t sxy = int64_t(d.nx) * d.ny;
     if (!skip) {
-        for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < d.M; e += int64_t(gridDim.x) * 256) {
-            const int i = int(e % d.nx), j = int((e / d.nx) % d.ny), k = int(e / sxy);
-            const double le = Lw[e];
-            double t = 0.0;
-            if (i < d.nx - 1) t -= le * r2[e];
-            if (i > 0) t += double(Lw[e - 1]) * r2[e - 1];
-            if (j < d.ny - 1) t -= le * r2[d.M + e];
-            if (j > 0) t += double(Lw[e - d.nx]) * r2[d.M + e - d.nx];
-            if (k < d.nz - 1) t -= le * r2[2 * d.M + e];
-            if (k > 0) t += double(Lw[e - sxy]) * r2[2 * d.M + e - sxy];
-            const T o = from_f32<T>(float(double(to_f32(s[e])) + lam * t));
-            s[e] = o;
-            const double f = to_f32(o);
-            acc += f * f;
+        TV_ROWS(d)
+        {
+            const int j = int(row % d.ny), k = int(row / d.ny);
+            for (int i = threadIdx.x; i < d.nx; i += 256) {
+                const int64_t e = row * d.nx + i;
+                const double le = Lw[e];
+                double t = 0.0;
+                if (i < d.nx - 1) t -= le * r2[e];
+                if (i > 0) t += double(Lw[e - 1]) * r2[e - 1];
+                if (j < d.ny - 1) t -= le * r2[d.M + e];
+                if (j > 0) t += double(Lw[e - d.nx]) * r2[d.M + e - d.nx];
+                if (k < d.nz - 1) t -= le * r2[2 * d.M + e];
+                if (k > 0) t += double(Lw[e - sxy]) * r2[2 * d.M + e - sxy];
+                const T o = from_f32<T>(float(double(to_f32(s[e])) + lam * t));
+                s[e] = o;
+                const double f = to_f32(o);
+                acc += f * f;
+            }
         }
     }
     acc = block_sum_tv(acc);
