@@ -234,6 +234,12 @@ typedef struct kct_solve_params {
  * from that row on, and column 0 holds the explicit residual throughout. */
 #define KCT_FLAG_STOP_ON_RESIDUAL_INCREASE 1u
 
+/* Record the explicit residual ||b - A x_k|| in history column 0 after every
+ * iteration without stopping (CGLS, LSQR, LSMR; Sec. 3.1.1 compares it with
+ * the recurred residual).  Costs one more forward projection per iteration.
+ * Implied by KCT_FLAG_STOP_ON_RESIDUAL_INCREASE. */
+#define KCT_FLAG_EXPLICIT_RESIDUAL 2u
+
 /* Workspace bytes kct_solve needs for `params` on `plan`. */
 kct_status kct_solve_workspace_bytes(const kct_plan *plan, const kct_solve_params *params,
                                      size_t *bytes);

@@ -25,6 +25,7 @@ KCT_F32, KCT_BF16, KCT_F16 = 0, 1, 2
 KCT_BP_MATCHED, KCT_BP_INTERP = 0, 1
 # flags
 KCT_FLAG_STOP_ON_RESIDUAL_INCREASE = 1
+KCT_FLAG_EXPLICIT_RESIDUAL = 2
 KCT_HIST_COLS = 5
 # kct_lambda_rule
 KCT_LAMBDA_FIXED, KCT_LAMBDA_GCV, KCT_LAMBDA_DP = 0, 1, 2

@@ -55,7 +55,10 @@ __device__ inline bool finite(double v) { return v == v && v - v == 0.0; }
 
 // The stencil kernels walk x-rows: workgroups stride over the ny*nz rows and
 // the threads over x, so the voxel coordinates cost one division per row
-// instead of a 64-bit division and modulo per voxel.
+// instead of a 64-bit division and modulo per voxel.  The row order is
+// XCD-aware: workgroup b runs on XCD b mod 8 (the grid is a multiple of 8) and
+// each XCD walks one contiguous eighth of the rows, so the z neighbours of a
+// row (one slice away) are mostly read through the same L2.
 
 __global__ __launch_bounds__(256) void k_fl_lap(const float *__restrict__ p, const float *__restrict__ Lw, Dims d,
                                                 float *__restrict__ q, double *parts)
@@ -64,28 +67,30 @@ __global__ __launch_bounds__(256) void k_fl_lap(const float *__restrict__ p, con
     const int64_t sxy = int64_t(d.nx) * d.ny;
     const int64_t rows = int64_t(d.ny) * d.nz;
     double acc = 0.0;
-    for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+    const int64_t per = (rows + 7) / 8, xcd = blockIdx.x & 7;
+    const int64_t end = rows < (xcd + 1) * per ? rows : (xcd + 1) * per;
+    for (int64_t row = xcd * per + (blockIdx.x >> 3); row < end; row += gridDim.x >> 3) {
         const int j = int(row % d.ny), k = int(row / d.ny);
         const int64_t e0 = row * d.nx;
+        // A missing neighbour (at the boundary) is the voxel itself, so its
+        // difference is exactly 0: every load is unconditional and they all
+        // issue before the first use.
+        const int64_t dyp = j < d.ny - 1 ? d.nx : 0, dym = j > 0 ? d.nx : 0;
+        const int64_t dzp = k < d.nz - 1 ? sxy : 0, dzm = k > 0 ? sxy : 0;
         for (int i = threadIdx.x; i < d.nx; i += 256) {
             const int64_t e = e0 + i;
+            const int64_t dxp = i < d.nx - 1 ? 1 : 0, dxm = i > 0 ? 1 : 0;
             const float c = p[e], le = Lw[e], we = le * le;
+            const float pxp = p[e + dxp], pxm = p[e - dxm], pyp = p[e + dyp], pym = p[e - dym];
+            const float pzp = p[e + dzp], pzm = p[e - dzm];
+            const float lx = Lw[e - dxm], ly = Lw[e - dym], lz = Lw[e - dzm];
             float t = 0.f;
-            if (i < d.nx - 1) t -= we * (p[e + 1] - c);
-            if (i > 0) {
-                const float l = Lw[e - 1];
-                t += l * l * (c - p[e - 1]);
-            }
-            if (j < d.ny - 1) t -= we * (p[e + d.nx] - c);
-            if (j > 0) {
-                const float l = Lw[e - d.nx];
-                t += l * l * (c - p[e - d.nx]);
-            }
-            if (k < d.nz - 1) t -= we * (p[e + sxy] - c);
-            if (k > 0) {
-                const float l = Lw[e - sxy];
-                t += l * l * (c - p[e - sxy]);
-            }
+            t -= we * (pxp - c);
+            t += lx * lx * (c - pxm);
+            t -= we * (pyp - c);
+            t += ly * ly * (c - pym);
+            t -= we * (pzp - c);
+            t += lz * lz * (c - pzm);
             q[e] = t;
             acc += double(c) * double(t);
         }
@@ -136,19 +141,32 @@ __global__ __launch_bounds__(256) void k_fl_dtl(const float *__restrict__ v3, co
     const int64_t sxy = int64_t(d.nx) * d.ny;
     const int64_t rows = int64_t(d.ny) * d.nz;
     double s1 = 0.0, s2 = 0.0;
-    for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+    const int64_t per = (rows + 7) / 8, xcd = blockIdx.x & 7;
+    const int64_t end = rows < (xcd + 1) * per ? rows : (xcd + 1) * per;
+    for (int64_t row = xcd * per + (blockIdx.x >> 3); row < end; row += gridDim.x >> 3) {
         const int j = int(row % d.ny), k = int(row / d.ny);
         const int64_t e0 = row * d.nx;
+        // Terms of missing neighbours are multiplied by 0 instead of skipped,
+        // so every load is unconditional (in bounds: the index is clamped to
+        // the voxel itself).
+        const float fyp = j < d.ny - 1 ? 1.f : 0.f, fym = j > 0 ? 1.f : 0.f;
+        const float fzp = k < d.nz - 1 ? 1.f : 0.f, fzm = k > 0 ? 1.f : 0.f;
+        const int64_t dym = j > 0 ? d.nx : 0, dzm = k > 0 ? sxy : 0;
         for (int i = threadIdx.x; i < d.nx; i += 256) {
             const int64_t e = e0 + i;
+            const float fxp = i < d.nx - 1 ? 1.f : 0.f, fxm = i > 0 ? 1.f : 0.f;
+            const int64_t dxm = i > 0 ? 1 : 0;
             const float le = Lw[e];
+            const float gx = v3[e], gy = v3[d.M + e], gz = v3[2 * d.M + e];
+            const float gxm = v3[e - dxm], gym = v3[d.M + e - dym], gzm = v3[2 * d.M + e - dzm];
+            const float lx = Lw[e - dxm], ly = Lw[e - dym], lz = Lw[e - dzm];
             float t = 0.f;
-            if (i < d.nx - 1) t -= le * v3[e];
-            if (i > 0) t += Lw[e - 1] * v3[e - 1];
-            if (j < d.ny - 1) t -= le * v3[d.M + e];
-            if (j > 0) t += Lw[e - d.nx] * v3[d.M + e - d.nx];
-            if (k < d.nz - 1) t -= le * v3[2 * d.M + e];
-            if (k > 0) t += Lw[e - sxy] * v3[2 * d.M + e - sxy];
+            t -= fxp * (le * gx);
+            t += fxm * (lx * gxm);
+            t -= fyp * (le * gy);
+            t += fym * (ly * gym);
+            t -= fzp * (le * gz);
+            t += fzm * (lz * gzm);
             out[e] = t;
             s1 += t;
             s2 += double(t) * t;
@@ -359,10 +377,11 @@ __global__ void k_sc_fl_hist(double *S, const double *M, int k, int ldm, double 
 
 } // namespace
 
+// A multiple of 8 workgroups (the XCD-aware row order needs it).
 int fl_groups(int64_t n)
 {
     const int64_t g = (n + 1023) / 1024;
-    return int(std::max<int64_t>(1, std::min<int64_t>(g, 2048)));
+    return int(std::max<int64_t>(8, std::min<int64_t>((g + 7) / 8 * 8, 2048)));
 }
 
 #define FL_CHECK(what) return check_hip(hipGetLastError(), what)

@@ -34,7 +34,7 @@ kct_status vk_combine(float *x, const void *basis, int dt, int64_t n, const doub
 
 kct_status vk_save_x(const float *x, float *xp, int64_t n, const double *S, hipStream_t st);
 kct_status vk_restore_x(float *x, const float *xp, int64_t n, const double *S, hipStream_t st);
-kct_status sk_explicit(double *S, Reduced r, double *hist, hipStream_t st);
+kct_status sk_explicit(double *S, Reduced r, double *hist, bool stop, hipStream_t st);
 kct_status sk_cgls_init(double *S, Reduced p, double lam, int n_iter, hipStream_t st);
 kct_status sk_cgls_alpha(double *S, Reduced q, Reduced p, hipStream_t st);
 kct_status sk_cgls_beta(double *S, Reduced s, Reduced r, double *hist, hipStream_t st);

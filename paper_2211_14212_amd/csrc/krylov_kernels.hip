@@ -462,10 +462,12 @@ __global__ __launch_bounds__(64) void k_hybrid_solve(double *S, const double *gk
 }
 
 // ---------------------------------------------------------------------------
-// Explicit-residual stop rule: x_prev = x before each iteration while the run
-// is live; after it, ||b - A x_k|| from the forward projector's partial sums;
-// when it exceeds the previous one the run is done (3) and x is put back to
-// x_prev on this and every later iteration (idempotent: x_prev no longer moves).
+// Explicit residual and stop rule: after each iteration ||b - A x_k|| comes
+// from the forward projector's partial sums into history column 0.  With the
+// stop rule, x_prev = x before each iteration while the run is live, and when
+// the residual exceeds the previous one the run is done (3) and x is put back
+// to x_prev on this and every later iteration (idempotent: x_prev no longer
+// moves).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_save_x(const float *__restrict__ x, float *__restrict__ xp, int64_t n,
                                                 const double *__restrict__ S)
@@ -481,14 +483,15 @@ __global__ __launch_bounds__(256) void k_restore_x(float *__restrict__ x, const 
     for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < n; e += int64_t(gridDim.x) * 256) x[e] = xp[e];
 }
 
-__global__ __launch_bounds__(256) void k_sc_explicit(double *S, const double *p, int64_t n, double *hist)
+__global__ __launch_bounds__(256) void k_sc_explicit(double *S, const double *p, int64_t n, double *hist,
+                                                    int stop)
 {
     const double r2 = reduce_parts(p, n);
     if (threadIdx.x != 0) return;
     const double r = sqrt(r2);
     if (S[S_DONE] == 0.0) {
         if (!finite(r)) S[S_DONE] = 2.0;
-        else if (S[S_PREV_EXPL] >= 0.0 && r > S[S_PREV_EXPL]) S[S_DONE] = 3.0;
+        else if (stop && S[S_PREV_EXPL] >= 0.0 && r > S[S_PREV_EXPL]) S[S_DONE] = 3.0;
         else S[S_PREV_EXPL] = r;
     }
     if (hist) {
@@ -963,9 +966,9 @@ kct_status vk_restore_x(float *x, const float *xp, int64_t n, const double *S, h
     hipLaunchKernelGGL(k_restore_x, dim3(vec_groups(n)), dim3(256), 0, st, x, xp, n, S);
     return check_hip(hipGetLastError(), "restore x");
 }
-kct_status sk_explicit(double *S, Reduced r, double *hist, hipStream_t st)
+kct_status sk_explicit(double *S, Reduced r, double *hist, bool stop, hipStream_t st)
 {
-    SC1(k_sc_explicit, dim3(1), dim3(256), 0, st, S, r.ptr, r.n, hist);
+    SC1(k_sc_explicit, dim3(1), dim3(256), 0, st, S, r.ptr, r.n, hist, stop ? 1 : 0);
     return check_hip(hipGetLastError(), "explicit residual");
 }
 kct_status sk_hybrid_choose(double *S, const double *gk, double *work, double *coef, double *hist, int rule,

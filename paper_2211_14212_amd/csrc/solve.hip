@@ -87,11 +87,12 @@ kct_status check_params(const kct_solve_params *prm)
         if (!is_gmres(prm->solver))
             return fail(KCT_E_INVALID_ARG, "only AB- and BA-GMRES take an unmatched back projector");
     }
-    if (prm->flags & ~KCT_FLAG_STOP_ON_RESIDUAL_INCREASE) return fail(KCT_E_INVALID_ARG, "unknown flags");
+    if (prm->flags & ~(KCT_FLAG_STOP_ON_RESIDUAL_INCREASE | KCT_FLAG_EXPLICIT_RESIDUAL))
+        return fail(KCT_E_INVALID_ARG, "unknown flags");
     if (prm->reserved != 0) return fail(KCT_E_INVALID_ARG, "reserved must be 0");
-    if ((prm->flags & KCT_FLAG_STOP_ON_RESIDUAL_INCREASE) && prm->solver != KCT_CGLS && prm->solver != KCT_LSQR &&
+    if (prm->flags && prm->solver != KCT_CGLS && prm->solver != KCT_LSQR &&
         prm->solver != KCT_LSMR)
-        return fail(KCT_E_INVALID_ARG, "the explicit-residual stop rule is for CGLS, LSQR and LSMR");
+        return fail(KCT_E_INVALID_ARG, "explicit residuals and the stop rule are for CGLS, LSQR and LSMR");
     if (is_sart(prm->solver)) {
         if (!(prm->lambda > 0.0 && prm->lambda < 2.0))
             return fail(KCT_E_INVALID_ARG, "SIRT / OS-SART need a relaxation lambda in (0, 2)");
@@ -139,7 +140,7 @@ Layout layout(const Plan &p, const kct_solve_params &prm)
     L.pb = o; o += up(sizeof(double) * L.nparts);
     L.pc = o; o += up(sizeof(double) * L.nparts);
     L.stage = o; o += up(sizeof(double) * 3 * 256);
-    const bool expl = prm.flags & KCT_FLAG_STOP_ON_RESIDUAL_INCREASE;
+    const bool expl = prm.flags & (KCT_FLAG_STOP_ON_RESIDUAL_INCREASE | KCT_FLAG_EXPLICIT_RESIDUAL);
     // The stop rule projects x itself (FP32), so its padded copy needs FP32.
     L.pad = o; o += up(size_t(2 * p.pad.vox) * (expl ? std::max<size_t>(vt, 4) : vt));
     const int k = prm.n_iter;
@@ -755,13 +756,14 @@ kct_status enqueue_init(kct_state &s)
 
 kct_status solver_iter(kct_state &s);
 
-// One iteration, with the explicit-residual stop rule around it when asked.
+// One iteration, with the explicit residual (and the stop rule) after it when asked.
 kct_status enqueue_iter(kct_state &s)
 {
-    if (!(s.prm.flags & KCT_FLAG_STOP_ON_RESIDUAL_INCREASE)) return solver_iter(s);
+    const bool stop = s.prm.flags & KCT_FLAG_STOP_ON_RESIDUAL_INCREASE;
+    if (!stop && !(s.prm.flags & KCT_FLAG_EXPLICIT_RESIDUAL)) return solver_iter(s);
     Plan &p = *s.plan;
     float *xp = static_cast<float *>(s.v(4));
-    KCT_TRY(vk_save_x(s.x, xp, s.M(), s.S(), s.st));
+    if (stop) KCT_TRY(vk_save_x(s.x, xp, s.M(), s.S(), s.st));
     KCT_TRY(solver_iter(s));
     Epilogue ef; // b - A x_k, with partial sums of its square
     ef.c[0] = -1.0;
@@ -770,8 +772,8 @@ kct_status enqueue_iter(kct_state &s)
     ef.partials = s.pa();
     KCT_TRY(launch_pad_volume(p, s.x, KCT_F32, s.pad(), s.st));
     KCT_TRY(launch_forward(p, s.pad(), KCT_F32, s.v(5), KCT_F32, ef, s.st));
-    KCT_TRY(sk_explicit(s.S(), red(s, s.pa(), fwd_num_groups(p), 0), s.hist, s.st));
-    return vk_restore_x(s.x, xp, s.M(), s.S(), s.st);
+    KCT_TRY(sk_explicit(s.S(), red(s, s.pa(), fwd_num_groups(p), 0), s.hist, stop, s.st));
+    return stop ? vk_restore_x(s.x, xp, s.M(), s.S(), s.st) : KCT_OK;
 }
 
 kct_status solver_iter(kct_state &s)

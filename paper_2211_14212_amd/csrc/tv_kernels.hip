@@ -36,18 +36,28 @@ struct Dims {
 
 // The kernels walk x-rows: workgroups stride over the ny*nz rows and the
 // threads over x, so voxel (i, j, k) costs one division per row instead of a
-// 64-bit division and modulo per voxel.
+// 64-bit division and modulo per voxel.  The row order is XCD-aware:
+// workgroup b runs on XCD b mod 8 (the grid is a multiple of 8) and each XCD
+// walks one contiguous eighth of the rows, so the z neighbours of a row (one
+// slice away) are mostly read through the same L2.
 #define TV_ROWS(d)                                                                                                 \
-    for (int64_t row = blockIdx.x, rows = int64_t(d.ny) * d.nz; row < rows; row += gridDim.x)
+    for (int64_t rows = int64_t(d.ny) * d.nz, per = (rows + 7) / 8, xcd = blockIdx.x & 7,                        \
+                 end = rows < (xcd + 1) * per ? rows : (xcd + 1) * per, row = xcd * per + (blockIdx.x >> 3);      \
+         row < end; row += gridDim.x >> 3)
 
 template <typename T>
 __device__ inline void grad_at(const T *x, Dims d, int64_t e, int i, int j, int k, float &gx, float &gy, float &gz)
 {
+    // The neighbour past the last index is the voxel itself (difference
+    // exactly 0), so the loads are unconditional and issue together.
     const int64_t sxy = int64_t(d.nx) * d.ny;
     const float c = to_f32(x[e]);
-    gx = i < d.nx - 1 ? to_f32(x[e + 1]) - c : 0.f;
-    gy = j < d.ny - 1 ? to_f32(x[e + d.nx]) - c : 0.f;
-    gz = k < d.nz - 1 ? to_f32(x[e + sxy]) - c : 0.f;
+    const float xp = to_f32(x[e + (i < d.nx - 1 ? 1 : 0)]);
+    const float yp = to_f32(x[e + (j < d.ny - 1 ? d.nx : 0)]);
+    const float zp = to_f32(x[e + (k < d.nz - 1 ? sxy : 0)]);
+    gx = xp - c;
+    gy = yp - c;
+    gz = zp - c;
 }
 
 // Lw = (|D x|^2 + eps^2)^{-1/4}.
@@ -132,16 +142,26 @@ __global__ __launch_bounds__(256) void k_tv_adjoint_add(T *__restrict__ s, const
         TV_ROWS(d)
         {
             const int j = int(row % d.ny), k = int(row / d.ny);
+            // Terms of missing neighbours are multiplied by 0 rather than
+            // skipped, so the loads are unconditional (clamped to the voxel).
+            const double fyp = j < d.ny - 1 ? 1.0 : 0.0, fym = j > 0 ? 1.0 : 0.0;
+            const double fzp = k < d.nz - 1 ? 1.0 : 0.0, fzm = k > 0 ? 1.0 : 0.0;
+            const int64_t dym = j > 0 ? d.nx : 0, dzm = k > 0 ? sxy : 0;
             for (int i = threadIdx.x; i < d.nx; i += 256) {
                 const int64_t e = row * d.nx + i;
+                const double fxp = i < d.nx - 1 ? 1.0 : 0.0, fxm = i > 0 ? 1.0 : 0.0;
+                const int64_t dxm = i > 0 ? 1 : 0;
                 const double le = Lw[e];
+                const double gx = r2[e], gy = r2[d.M + e], gz = r2[2 * d.M + e];
+                const double gxm = r2[e - dxm], gym = r2[d.M + e - dym], gzm = r2[2 * d.M + e - dzm];
+                const double lx = Lw[e - dxm], ly = Lw[e - dym], lz = Lw[e - dzm];
                 double t = 0.0;
-                if (i < d.nx - 1) t -= le * r2[e];
-                if (i > 0) t += double(Lw[e - 1]) * r2[e - 1];
-                if (j < d.ny - 1) t -= le * r2[d.M + e];
-                if (j > 0) t += double(Lw[e - d.nx]) * r2[d.M + e - d.nx];
-                if (k < d.nz - 1) t -= le * r2[2 * d.M + e];
-                if (k > 0) t += double(Lw[e - sxy]) * r2[2 * d.M + e - sxy];
+                t -= fxp * (le * gx);
+                t += fxm * (lx * gxm);
+                t -= fyp * (le * gy);
+                t += fym * (ly * gym);
+                t -= fzp * (le * gz);
+                t += fzm * (lz * gzm);
                 const T o = from_f32<T>(float(double(to_f32(s[e])) + lam * t));
                 s[e] = o;
                 const double f = to_f32(o);
@@ -194,10 +214,11 @@ __global__ __launch_bounds__(256) void k_sc_tv_alpha(double *S, const double *pq
     S[S_V3] = -alpha * lam;  // r2 += V3 L D p
 }
 
+// A multiple of 8 workgroups (the XCD-aware row order needs it).
 int tv_groups(int64_t n)
 {
     const int64_t g = (n + 1023) / 1024;
-    return int(std::max<int64_t>(1, std::min<int64_t>(g, VEC_GROUPS)));
+    return int(std::max<int64_t>(8, std::min<int64_t>((g + 7) / 8 * 8, VEC_GROUPS)));
 }
 
 } // namespace

@@ -9,6 +9,10 @@ so kernels of different requests overlap on the GPU.  A request leaves when
 its last iteration has run on the device; its memory is freed and queued
 requests are admitted in its place.  Each request's result is bitwise the
 same as a solo kct_solve of it (deterministic kernels, private buffers).
+A request can be cancelled (``Server.cancel``): no further iteration of it is
+enqueued, and once its last enqueued one has run its memory is freed and it
+returns a result marked ``cancelled`` with no image.  The other requests are
+unaffected, bit for bit.
 
 Latency = completion time - arrival time.  The serial baseline runs the same
 stream through the plain per-request path (one kct_solve at a time, FIFO).
@@ -53,6 +57,7 @@ class Result:
     finished: float
     x: torch.Tensor | None
     history: torch.Tensor | None
+    cancelled: bool = False
 
     @property
     def latency(self) -> float:
@@ -84,9 +89,19 @@ class Server:
         self.keep_results = keep_results
         self.verbose = verbose
         self.log = []
+        self._cancel: set[int] = set()
 
-    def run(self, requests: list[Request]) -> list[Result]:
-        """Serve `requests` (sorted by arrival) in real time; returns results by id."""
+    def cancel(self, req_id: int) -> None:
+        """Cancel a request (queued or active); safe to call while ``run`` serves."""
+        self._cancel.add(req_id)
+
+    def run(self, requests: list[Request], cancel_after: dict[int, int] | None = None) -> list[Result]:
+        """Serve `requests` (sorted by arrival) in real time; returns results by id.
+
+        ``cancel_after`` maps a request id to an iteration count: the request
+        is cancelled once that many of its iterations are enqueued (a
+        deterministic trigger for ``cancel``)."""
+        cancel_after = dict(cancel_after or {})
         pending = deque(sorted(requests, key=lambda r: r.arrival))
         queue: deque[Request] = deque()
         active: list[_Active] = []
@@ -98,6 +113,11 @@ class Server:
                 now = time.perf_counter() - t0
                 while pending and pending[0].arrival <= now:
                     queue.append(pending.popleft())
+                # Cancelled requests still waiting leave at once.
+                for req in [q for q in queue if q.id in self._cancel]:
+                    queue.remove(req)
+                    results[req.id] = Result(req.id, req.arrival, now, now, None, None, cancelled=True)
+                    self.log.append(("cancel", req.id, now, used))
                 # Admission: FIFO while the head fits the budget.
                 while queue and len(active) < self.max_active:
                     req = queue[0]
@@ -116,6 +136,10 @@ class Server:
                 # Advance every active request whose previous step has finished.
                 progressed = False
                 for a in active:
+                    if cancel_after.get(a.req.id, -1) == a.enqueued:
+                        self._cancel.add(a.req.id)
+                    if a.req.id in self._cancel:
+                        continue
                     if a.enqueued < a.req.n_iter and (a.event is None or a.event.query()):
                         a.state.step(1)
                         a.enqueued += 1
@@ -130,16 +154,19 @@ class Server:
                 # Retire requests whose last iteration has completed.
                 still = []
                 for a in active:
-                    done_enq = a.enqueued == a.req.n_iter or a.enqueued == -1
-                    if done_enq and a.event is not None and a.event.query():
+                    cancelled = a.req.id in self._cancel
+                    done_enq = a.enqueued == a.req.n_iter or a.enqueued == -1 or cancelled
+                    if done_enq and (a.event is None or a.event.query()):
                         fin = time.perf_counter() - t0
-                        x = a.state.x if self.keep_results else None
-                        h = a.state.history if self.keep_results else None
-                        results[a.req.id] = Result(a.req.id, a.req.arrival, a.admitted, fin, x, h)
+                        keep = self.keep_results and not cancelled
+                        x = a.state.x if keep else None
+                        h = a.state.history if keep else None
+                        results[a.req.id] = Result(a.req.id, a.req.arrival, a.admitted, fin, x, h, cancelled)
+                        a.stream.synchronize()  # the workspace is returned only once idle
                         a.state.close()
                         a.plan.close()
                         used -= a.nbytes
-                        self.log.append(("finish", a.req.id, fin, used))
+                        self.log.append(("cancel" if cancelled else "finish", a.req.id, fin, used))
                         if self.verbose and (len(results) % 8 == 0 or len(results) == len(requests)):
                             print(f"[serve] batched: {len(results)}/{len(requests)} done at {fin:.1f} s",
                                   file=sys.stderr, flush=True)
@@ -189,6 +216,7 @@ def percentile(values, q):
 
 
 def summarize(results: list[Result]) -> dict:
+    results = [r for r in results if not r.cancelled]
     lat = [r.latency for r in results]
     makespan = max(r.finished for r in results) - min(r.arrival for r in results)
     return {"n": len(results), "p50_s": percentile(lat, 50), "p99_s": percentile(lat, 99),

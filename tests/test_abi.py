@@ -54,6 +54,7 @@ def test_header_constants_match_binding():
     assert ctypes.sizeof(_lib.KctSolveParams) == 4 + 4 + 8 + 4 + 4 + 8 + 4 + 4 + 8 + 4 + 4 + 4 + 4
     assert int(re.search(r"#define KCT_FLAG_STOP_ON_RESIDUAL_INCREASE (\d+)u", src).group(1)) == \
         _lib.KCT_FLAG_STOP_ON_RESIDUAL_INCREASE
+    assert int(re.search(r"#define KCT_FLAG_EXPLICIT_RESIDUAL (\d+)u", src).group(1)) == _lib.KCT_FLAG_EXPLICIT_RESIDUAL
 
 
 def test_status_strings_and_version():

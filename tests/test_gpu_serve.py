@@ -1,6 +1,7 @@
 """Continuous-batching server on the GPU: each request's result is bitwise the
-same alone and in the mix; admission never exceeds the HBM budget; a small
-request is spot-checked against the FP64 oracle."""
+same alone and in the mix; admission never exceeds the HBM budget; cancelling
+a request mid-flight leaves the others bitwise unchanged; a small request is
+spot-checked against the FP64 oracle."""
 import numpy as np
 import pytest
 import torch
@@ -51,6 +52,29 @@ def test_budget_respected(stream):
     assert len(res) == len(reqs)
     assert max(u for (_, _, _, u) in srv.log) <= budget
     assert len([a for a in srv.log if a[0] == "admit"]) == len(reqs)
+
+
+def test_cancel_leaves_others_bitwise(stream):
+    serve, reqs = stream
+    victim, early = reqs[1].id, reqs[-1].id
+    srv = serve.Server(budget_bytes=50e9, max_active=6)
+    srv.cancel(early)  # cancelled before it is ever stepped
+    res = srv.run(reqs, cancel_after={victim: 2})
+    assert len(res) == len(reqs)
+    for req, r in zip(reqs, res):
+        if req.id in (victim, early):
+            assert r.cancelled and r.x is None and r.history is None, req.id
+            continue
+        assert not r.cancelled
+        plan = serve.Plan(req.geom)
+        x, h = plan.solve(req.b, req.solver, req.n_iter, req.lam)
+        torch.cuda.synchronize()
+        assert torch.equal(r.x, x), req.id
+        assert torch.equal(r.history, h), req.id
+    events = [(e[0], e[1]) for e in srv.log]
+    assert ("cancel", victim) in events and ("cancel", early) in events
+    assert srv.log[-1][3] == 0  # every byte of the budget is returned
+    assert serve.summarize(res)["n"] == len(reqs) - 2
 
 
 def test_small_request_matches_oracle(stream):

@@ -91,7 +91,35 @@ def test_rule_rejected_where_it_does_not_apply(kct):
         with pytest.raises(kct._lib.KctError):
             plan.solve(bt, solver, 3, lam, stop_on_residual_increase=True, **kw)
     lib = kct._lib.load()
-    for flags, reserved in ((2, 0), (1, 7)):
+    for flags, reserved in ((4, 0), (1, 7)):
         p = kct._lib.KctSolveParams(kct._lib.KCT_CGLS, 3, 0.0, 0, 0, 1e-3, 0, 0, 0.0, 0, 0, flags, reserved)
         n = ctypes.c_size_t()
         assert lib.kct_solve_workspace_bytes(plan.handle, ctypes.byref(p), ctypes.byref(n)) != 0
+
+
+@pytest.mark.parametrize("solver", ["cgls", "lsqr"])
+def test_explicit_residual_flag_records_without_stopping(kct, solver):
+    """KCT_FLAG_EXPLICIT_RESIDUAL alone: column 0 holds ||b - A x_k|| (checked
+    with the plain forward projector after 6 iterations, far above the FP32
+    floor where two correct evaluations differ by their own rounding), the
+    iterates are those of the run without the flag, and a long run goes on
+    through the increases that stop the rule on this problem."""
+    gd = synth.geometry(dict(nx=8, ny=8, nz=2, vx=1.0, vy=1.0, vz=1.0, nu=16, nv=4, du=1.0, dv=1.0, dso=40.0,
+                             dsd=60.0, n_angles=12))
+    og = oracle.Geometry.from_dict(gd)
+    b = oracle.forward(og, synth.random_volume(og.vol_shape, 3)).astype(np.float32)
+    plan = kct.Plan(kct.Geometry.from_dict(gd))
+    bt = torch.from_numpy(b).to(DEV)
+    n = 120
+    x0, _ = plan.solve(bt, solver, n)
+    x1, h1 = plan.solve(bt, solver, n, explicit_residual=True)
+    x6, h6 = plan.solve(bt, solver, 6, explicit_residual=True)
+    r = torch.linalg.vector_norm((plan.forward(x6) - bt).double())
+    torch.cuda.synchronize()
+    h1, h6 = h1.cpu().numpy(), h6.cpu().numpy()
+    assert torch.equal(x0, x1)
+    assert np.all(h1[:, 3] == 0)
+    assert np.any(np.diff(h1[:, 0]) > 0)
+    print(f"[explicit {solver}] 6 iterations: recorded {h6[-1, 0]:.6e}, recomputed {float(r):.6e}", flush=True)
+    assert h6[-1, 0] > 1e-3 * float(torch.linalg.vector_norm(bt.double()))
+    np.testing.assert_allclose(h6[-1, 0], float(r), rtol=1e-5)
