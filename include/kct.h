@@ -31,7 +31,10 @@
  *
  * Streams.  Every call that takes a `stream` (a hipStream_t, or NULL for the
  * null stream) only enqueues work on it and returns; the caller synchronises.
- * Calls on one plan must not overlap in time unless they use different plans.
+ * kct_forward calls on one plan share the plan's padded volume copies, so
+ * they must not overlap in time (use one plan per stream for that).  Solves
+ * keep their copies in their own workspace and only read the plan, so solves
+ * on one plan may run concurrently on different streams.
  *
  * Errors.  Argument and geometry checks happen before anything is enqueued and
  * return a status; kct_last_error() then holds a message for the calling
@@ -58,8 +61,9 @@ typedef enum kct_status {
     KCT_E_OOM = 4,         /* device allocation by the library failed               */
     KCT_E_BUDGET = 5,      /* a caller-provided buffer is too small                 */
     KCT_E_DEVICE = 6,      /* a HIP call or kernel launch failed                    */
-    KCT_E_NONFINITE = 7,   /* the solver met a NaN or Inf (e.g. in b)               */
-    KCT_E_STATE = 8        /* call made on a state in the wrong phase               */
+    KCT_E_NONFINITE = 7,   /* reserved: a solver that meets a NaN or Inf reports it
+                              in history column 3 (the host never waits on it)    */
+    KCT_E_STATE = 8        /* reserved                                              */
 } kct_status;
 
 /* Storage types of device vectors.  Arithmetic is FP32 for ray and voxel

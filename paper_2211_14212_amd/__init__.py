@@ -12,7 +12,6 @@ from __future__ import annotations
 
 import ctypes
 import dataclasses
-import math
 
 import numpy as np
 import torch

@@ -2,7 +2,6 @@
 backward is the matched back projector), on the 64^3 crop of the uCT-shaped
 workload: the adjoint test, linear finite differences, and central finite
 differences through a nonlinear Beer-Lambert loss."""
-import numpy as np
 import pytest
 import torch
 

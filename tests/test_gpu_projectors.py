@@ -7,7 +7,6 @@ the whole output a relative L2 error of a few 1e-7.  The gate is 1e-6
 relative L2 (and 2e-6 of the output's max per element); 16-bit storage adds
 its own output rounding (2^-8 BF16, 2^-11 FP16).
 """
-import math
 
 import numpy as np
 import pytest
