@@ -108,6 +108,23 @@ def test_bitwise_deterministic(kct):
     assert torch.equal(plan.backproject(y), plan.backproject(y))
 
 
+@pytest.mark.parametrize("name", ["ragged", "face_planes", "muct_crop"])
+def test_forward_gather_depths_agree_bitwise(kct, name, monkeypatch):
+    """The forward loop with and without the one-step-ahead gather
+    (KCT_FWD_PREFETCH, read at plan creation) loads the same voxels and adds
+    the same segments in the same order: the projections are bitwise equal."""
+    gd = _geoms()[name]
+    x = torch.from_numpy(synth.random_volume(tuple(gd[k] for k in ("nz", "ny", "nx")), 7)).to(DEV)
+    outs = []
+    for depth in ("0", "1"):
+        monkeypatch.setenv("KCT_FWD_PREFETCH", depth)
+        plan = kct.Plan(kct.Geometry.from_dict(gd))
+        outs.append(plan.forward(x))
+        torch.cuda.synchronize()
+        plan.close()
+    assert torch.equal(outs[0], outs[1])
+
+
 @pytest.mark.parametrize("dt,tol", [(torch.bfloat16, 6e-3), (torch.float16, 8e-4)])
 def test_16bit_storage(kct, dt, tol):
     """16-bit inputs and outputs, FP32 accumulation: error = storage rounding."""
