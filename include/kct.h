@@ -284,6 +284,23 @@ kct_status kct_state_step(kct_state *state, int32_t n_steps);
 /* Iterations enqueued so far and whether all requested iterations are. */
 kct_status kct_state_progress(const kct_state *state, int32_t *iters_enqueued, int32_t *finished);
 
+/*
+ * Checkpoint and resume (serving preemption, long runs).  A run's whole
+ * device state lives in the caller's buffers: the workspace, x and the
+ * history.  To checkpoint, make sure the initialisation and `iters_done`
+ * iterations have been enqueued (kct_state_step, at least once), wait for
+ * the stream, and copy every byte of the three buffers.  To resume, copy them
+ * back into buffers of the same sizes (any addresses, any later time, a new
+ * plan of the same geometry) and call kct_state_resume with the same params
+ * and b: nothing is enqueued, and the following kct_state_step calls continue
+ * with iteration iters_done + 1, bitwise as the uninterrupted run would.
+ * 0 <= iters_done <= the run's iteration count; KCT_E_INVALID_ARG otherwise.
+ * The other arguments are as for kct_state_create.
+ */
+kct_status kct_state_resume(kct_plan *plan, const kct_solve_params *params, const void *d_b, void *d_x,
+                            void *d_ws, size_t ws_bytes, double *d_history, void *stream, int32_t iters_done,
+                            kct_state **out);
+
 /* Release a state (not the caller's buffers).  NULL is accepted. */
 kct_status kct_state_destroy(kct_state *state);
 

@@ -245,15 +245,21 @@ class Plan:
     def state(self, b, solver="cgls", n_iter=20, lam=0.0, vec_dtype=torch.float32, stream=None, **tv) -> "State":
         return State(self, b, solver, n_iter, lam, vec_dtype, stream, **tv)
 
+    def resume_state(self, b, checkpoint: dict, stream=None) -> "State":
+        """A State continuing a run from ``State.checkpoint()`` (same geometry, same b)."""
+        c = checkpoint
+        return State(self, b, c["solver"], c["n_iter"], c["lam"], c["vec_dtype"], stream, _resume=c, **c["options"])
+
 
 class State:
     """Iteration-level solver run (kct_state_*), owning its buffers as tensors."""
 
-    def __init__(self, plan: Plan, b, solver, n_iter, lam, vec_dtype, stream=None, **tv):
+    def __init__(self, plan: Plan, b, solver, n_iter, lam, vec_dtype, stream=None, _resume=None, **tv):
         plan._check(b, plan.geom.proj_shape, "b")
         self.plan = plan
         self.b = b
         self.n_iter = n_iter
+        self._args = dict(solver=solver, n_iter=n_iter, lam=lam, vec_dtype=vec_dtype, options=dict(tv))
         self.stream = stream if stream is not None else torch.cuda.current_stream(plan.device)
         self.x = torch.empty(plan.geom.vol_shape, dtype=torch.float32, device=plan.device)
         need = plan.workspace_bytes(solver, n_iter, lam, vec_dtype, **tv)
@@ -262,13 +268,30 @@ class State:
         self.history = torch.zeros((max(rows, 1), KCT_HIST_COLS), dtype=torch.float64, device=plan.device)
         p = _params(solver, n_iter, lam, vec_dtype, **tv)
         h = ctypes.c_void_p()
-        _lib.check(_lib.load().kct_state_create(plan.handle, ctypes.byref(p), ctypes.c_void_p(b.data_ptr()),
-                                                ctypes.c_void_p(self.x.data_ptr()),
-                                                ctypes.c_void_p(self.workspace.data_ptr()), need,
-                                                ctypes.c_void_p(self.history.data_ptr()),
-                                                ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
-                   "kct_state_create")
+        args = (plan.handle, ctypes.byref(p), ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(self.x.data_ptr()),
+                ctypes.c_void_p(self.workspace.data_ptr()), need, ctypes.c_void_p(self.history.data_ptr()),
+                ctypes.c_void_p(self.stream.cuda_stream))
+        if _resume is None:
+            _lib.check(_lib.load().kct_state_create(*args, ctypes.byref(h)), "kct_state_create")
+        else:
+            if _resume["workspace"].numel() != need or _resume["history"].shape != self.history.shape:
+                raise ValueError("checkpoint does not match this run's buffer sizes")
+            with torch.cuda.stream(self.stream):
+                self.workspace.copy_(_resume["workspace"])
+                self.x.copy_(_resume["x"])
+                self.history.copy_(_resume["history"])
+            _lib.check(_lib.load().kct_state_resume(*args, int(_resume["iters"]), ctypes.byref(h)),
+                       "kct_state_resume")
         self._h = h
+
+    def checkpoint(self) -> dict:
+        """Host copy of the run's whole state (workspace, x, history) and its
+        arguments; waits for the stream.  ``Plan.resume_state`` continues it."""
+        self.step(0)  # the initialisation, if it has not been enqueued yet
+        self.stream.synchronize()
+        it, _ = self.progress()
+        return dict(self._args, iters=it, workspace=self.workspace.cpu(), x=self.x.cpu(),
+                    history=self.history.cpu())
 
     def step(self, n: int = 1):
         with torch.cuda.device(self.plan.device):

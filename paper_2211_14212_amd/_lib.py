@@ -34,6 +34,7 @@ EXPORTED = [
     "kct_plan_create", "kct_plan_destroy", "kct_plan_device_bytes", "kct_forward", "kct_backproject",
     "kct_backproject_interp",
     "kct_solve_workspace_bytes", "kct_solve", "kct_state_create", "kct_state_step", "kct_state_progress",
+    "kct_state_resume",
     "kct_state_destroy", "kct_status_str", "kct_last_error", "kct_version",
 ]
 
@@ -94,6 +95,7 @@ def load(path: str = LIB_PATH):
         "kct_state_create": ([vp, P(KctSolveParams), vp, vp, vp, sz, vp, vp, P(vp)], st),
         "kct_state_step": ([vp, i32], st),
         "kct_state_progress": ([vp, P(i32), P(i32)], st),
+        "kct_state_resume": ([vp, P(KctSolveParams), vp, vp, vp, sz, vp, vp, i32, P(vp)], st),
         "kct_state_destroy": ([vp], st),
         "kct_status_str": ([st], ctypes.c_char_p),
         "kct_last_error": ([], ctypes.c_char_p),

@@ -567,18 +567,16 @@ float *sa_V(kct_state &s, int k) { return static_cast<float *>(s.v(3)) + size_t(
 const float *sa_b(kct_state &s) { return sa_m(s) > 1 ? static_cast<const float *>(s.v(4)) : s.b; }
 size_t sa_off(const kct_state &s, int k) { return size_t(s.sub_a0[k]) * size_t(s.plan->gp.nv) * s.plan->gp.nu; }
 
-kct_status sa_init(kct_state &s)
+// The host side of SART's set-up: subset k holds the angles a = k, k + m, ...,
+// laid out as the k-th contiguous block of the permuted order (its table in
+// the workspace when m > 1); s.sub[k] is the plan restricted to that block.
+void sa_views(kct_state &s)
 {
     Plan &p = *s.plan;
     const int m = sa_m(s), na = p.gp.na;
-    // Subset k: angles a = k, k + m, ...; laid out as the k-th contiguous block.
     s.sub_a0.clear();
     for (int k = 0; k <= m; ++k) s.sub_a0.push_back(k < m ? sa_block_start(k, na, m) : na);
-    AngleGeo *tab = p.d_tab;
-    if (m > 1) {
-        tab = reinterpret_cast<AngleGeo *>(s.ws + s.L.work);
-        KCT_TRY(sa_permute(tab, p.d_tab, static_cast<float *>(s.v(4)), s.b, na, int64_t(p.gp.nv) * p.gp.nu, m, s.st));
-    }
+    AngleGeo *tab = m > 1 ? reinterpret_cast<AngleGeo *>(s.ws + s.L.work) : p.d_tab;
     s.sub.assign(m, p);
     for (int k = 0; k < m; ++k) {
         Plan &v = s.sub[k];
@@ -586,6 +584,16 @@ kct_status sa_init(kct_state &s)
         v.gp.na = s.sub_a0[k + 1] - s.sub_a0[k];
         v.bwd_fp_angles = std::min(v.bwd_fp_angles, v.gp.na);
     }
+}
+
+kct_status sa_init(kct_state &s)
+{
+    Plan &p = *s.plan;
+    const int m = sa_m(s), na = p.gp.na;
+    sa_views(s);
+    if (m > 1)
+        KCT_TRY(sa_permute(reinterpret_cast<AngleGeo *>(s.ws + s.L.work), p.d_tab, static_cast<float *>(s.v(4)),
+                           s.b, na, int64_t(p.gp.nv) * p.gp.nu, m, s.st));
     Epilogue plain;
     // W = 1 / (A 1): every block's rays through a volume of ones.
     KCT_TRY(vk_fill(sa_v(s), KCT_F32, s.M(), 1.f, s.st));
@@ -841,6 +849,26 @@ kct_status kct_state_create(kct_plan *plan, const kct_solve_params *params, cons
     s->st = static_cast<hipStream_t>(stream);
     s->L = L;
     s->total = params->solver == KCT_IRN_TV_CGLS ? params->tv_outer * params->tv_inner : params->n_iter;
+    *out = s;
+    return KCT_OK;
+}
+
+kct_status kct_state_resume(kct_plan *plan, const kct_solve_params *params, const void *d_b, void *d_x,
+                            void *d_ws, size_t ws_bytes, double *d_history, void *stream, int32_t iters_done,
+                            kct_state **out)
+{
+    if (out) *out = nullptr;
+    kct_state *s = nullptr;
+    KCT_TRY(kct_state_create(plan, params, d_b, d_x, d_ws, ws_bytes, d_history, stream, &s));
+    if (iters_done < 0 || iters_done > s->total) {
+        kct_state_destroy(s);
+        return fail(KCT_E_INVALID_ARG, "iters_done outside 0..the run's iteration count");
+    }
+    // Host-side set-up only: the device state is already in the buffers.
+    if (is_sart(s->prm.solver)) sa_views(*s);
+    s->started = true;
+    s->enqueued = iters_done;
+    s->finalized = iters_done == s->total;
     *out = s;
     return KCT_OK;
 }

@@ -169,3 +169,39 @@ def test_solve_bitwise_deterministic(kct):
     x2, h2 = plan.solve(bt, "lsmr", 10)
     torch.cuda.synchronize()
     assert torch.equal(x1, x2) and torch.equal(h1, h2)
+
+
+@pytest.mark.parametrize("solver,kw,k", [
+    ("cgls", {}, 4), ("cgls", {}, 0), ("lsqr", {"lam": 0.5}, 4), ("lsmr", {}, 4), ("hybrid_lsqr", {"lam": 0.5}, 4),
+    ("hybrid_lsqr", {"lam_rule": "gcv"}, 4), ("ab_gmres", {"backprojector": "interp"}, 4),
+    ("os_sart", {"lam": 1.0, "n_subsets": 4}, 4), ("irn_tv_cgls", {"lam": 0.5, "tv_outer": 3, "tv_inner": 4}, 6),
+    ("hybrid_flsqr_tv", {"lam": 1.0, "tv_inner": 5, "tv_eps": 0.1}, 4),
+    ("cgls", {"stop_on_residual_increase": True}, 4)])
+def test_checkpoint_resume_bitwise(kct, solver, kw, k):
+    """k iterations, a host checkpoint of the workspace, x and history, the
+    state destroyed, then resumed on a new plan of the same geometry (b at
+    another address) and run to the end: bitwise the uninterrupted run."""
+    og, kg, b = _problem("cgls32")
+    plan = kct.Plan(kg)
+    bt = torch.from_numpy(b).to(DEV)
+    kw = dict(kw)
+    lam = kw.pop("lam", 0.0)
+    n = 0 if solver == "irn_tv_cgls" else 10
+    total = kw["tv_outer"] * kw["tv_inner"] if solver == "irn_tv_cgls" else n
+    st = plan.state(bt, solver, n, lam, **kw)
+    st.step(k)
+    ckpt = st.checkpoint()
+    assert ckpt["iters"] == k and ckpt["workspace"].device.type == "cpu"
+    st.close()
+    del st
+    plan2 = kct.Plan(kg)
+    r = plan2.resume_state(bt.clone(), ckpt)
+    r.step(total)
+    assert r.progress() == (total, True)
+    x2, h2 = plan.solve(bt, solver, n, lam, **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(r.x, x2), solver
+    assert torch.equal(r.history, h2), solver
+    bad = dict(ckpt, iters=total + 1)
+    with pytest.raises(kct._lib.KctError):
+        plan2.resume_state(bt, bad)
