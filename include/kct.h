@@ -31,10 +31,11 @@
  *
  * Streams.  Every call that takes a `stream` (a hipStream_t, or NULL for the
  * null stream) only enqueues work on it and returns; the caller synchronises.
- * kct_forward calls on one plan share the plan's padded volume copies, so
- * they must not overlap in time (use one plan per stream for that).  Solves
- * keep their copies in their own workspace and only read the plan, so solves
- * on one plan may run concurrently on different streams.
+ * kct_forward and kct_backproject calls on one plan share the plan's scratch
+ * (the padded volume copies; for small volumes, the back projector's partial
+ * volumes), so they must not overlap in time (use one plan per stream for
+ * that).  Solves keep that scratch in their own workspace and only read the
+ * plan, so solves on one plan may run concurrently on different streams.
  *
  * Errors.  Argument and geometry checks happen before anything is enqueued and
  * return a status; kct_last_error() then holds a message for the calling
@@ -102,7 +103,8 @@ kct_status kct_plan_create(const kct_geometry *geom, int device, kct_plan **out)
 /* Free a plan and every device buffer it owns.  NULL is accepted. */
 kct_status kct_plan_destroy(kct_plan *plan);
 
-/* Device bytes the plan holds now (tables and padded volume copies). */
+/* Device bytes the plan holds now (tables, padded volume copies and partial
+ * volumes of plain kct_forward / kct_backproject calls). */
 kct_status kct_plan_device_bytes(const kct_plan *plan, size_t *bytes);
 
 /*
@@ -118,7 +120,9 @@ kct_status kct_forward(kct_plan *plan, const void *d_vol, int32_t vol_dtype, voi
  * Back projection with the exact transpose of kct_forward (paper Sec. 2.1.4
  * and Sec. 4: a mismatched back projector degrades the Krylov methods):
  * d_vol = A^T d_proj.  Voxel-driven gather; FP32 accumulation.  Layouts as in
- * kct_forward; d_vol is overwritten.  Enqueued on `stream`.
+ * kct_forward; d_vol is overwritten.  For a small volume (too few voxel tiles
+ * to fill the GPU) the angles are split over up to 16 chunks whose partial
+ * volumes are summed in chunk order.  Enqueued on `stream`.
  */
 kct_status kct_backproject(kct_plan *plan, const void *d_proj, int32_t proj_dtype, void *d_vol,
                            int32_t vol_dtype, void *stream);

@@ -210,6 +210,7 @@ kct_status kct_plan_destroy(kct_plan *p)
     if (p->d_invv) (void)hipFree(p->d_invv);
     if (p->d_err) (void)hipFree(p->d_err);
     if (p->d_pad) (void)hipFree(p->d_pad);
+    if (p->d_split) (void)hipFree(p->d_split);
     delete p;
     return KCT_OK;
 }
@@ -217,7 +218,7 @@ kct_status kct_plan_destroy(kct_plan *p)
 kct_status kct_plan_device_bytes(const kct_plan *p, size_t *bytes)
 {
     if (!p || !bytes) return fail(KCT_E_INVALID_ARG, "NULL argument");
-    *bytes = sizeof(AngleGeo) * p->gp.na + sizeof(double) * p->gp.nv + sizeof(int) + p->pad_bytes;
+    *bytes = sizeof(AngleGeo) * p->gp.na + sizeof(double) * p->gp.nv + sizeof(int) + p->pad_bytes + p->split_bytes;
     return KCT_OK;
 }
 
@@ -252,6 +253,18 @@ kct_status kct_backproject(kct_plan *p, const void *d_proj, int32_t proj_dtype, 
     if (!dtype_ok(vol_dtype) || !dtype_ok(proj_dtype)) return fail(KCT_E_DTYPE, "unknown storage type");
     DeviceGuard dg(p->device);
     Epilogue ep;
+    // Partial volumes of the angle-split back projection (small volumes),
+    // owned by the plan like the forward's padded copies.
+    const size_t need = sizeof(float) * size_t(bwd_split_floats(*p));
+    if (p->split_bytes < need) {
+        if (p->d_split) (void)hipFree(p->d_split);
+        p->d_split = nullptr;
+        p->split_bytes = 0;
+        kct_status s = check_hip(hipMalloc(&p->d_split, need), "partial volume allocation");
+        if (s != KCT_OK) return s;
+        p->split_bytes = need;
+    }
+    ep.split = p->d_split;
     return launch_backward(*p, d_proj, proj_dtype, d_vol, vol_dtype, ep, static_cast<hipStream_t>(stream));
 }
 

@@ -105,6 +105,9 @@ struct Plan {
     int *d_err = nullptr;         // back projector footprint overflow flag (0 = fine)
     // Back projector launch shape (chosen from the geometry at plan creation).
     int bwd_kz = 8, bwd_ncmax = 5, bwd_pw = 0, bwd_ph = 0, bwd_fp_angles = 0;
+    int bwd_asplit = 1;           // angle chunks of the back projector (small volumes: > 1)
+    float *d_split = nullptr;     // partial volumes for plain kct_backproject calls
+    size_t split_bytes = 0;       // capacity of d_split
     bool fwd_prefetch = true;     // forward projector gathers one segment ahead
     int fwd_lane_u = 16;          // forward wave patch: lane_u x (64 / lane_u) rays (64, 32 or 16)
     bool bwd_acc_lds = true;      // back projector keeps per-voxel sums in LDS
@@ -125,6 +128,7 @@ struct Epilogue {
     const float *in2 = nullptr;   // FP32 (e.g. x)
     const void *in3 = nullptr;    // same storage type as out
     double *partials = nullptr;   // per-workgroup sum of out^2, or null
+    float *split = nullptr;       // back projector: bwd_split_floats(plan) floats of partial volumes
 };
 
 // Thread-local error text.
@@ -139,6 +143,9 @@ int64_t fwd_num_groups(const Plan &p);
 kct_status launch_forward(Plan &p, const void *pad, int vol_dtype, void *proj, int proj_dtype,
                           const Epilogue &ep, hipStream_t st);
 int64_t bwd_num_groups(const Plan &p);
+// Floats of partial volumes the back projector needs in Epilogue::split (0
+// when it does not split the angles).
+int64_t bwd_split_floats(const Plan &p);
 kct_status launch_backward(Plan &p, const void *proj, int proj_dtype, void *vol, int vol_dtype,
                            const Epilogue &ep, hipStream_t st);
 kct_status choose_bwd_shape(Plan &p);

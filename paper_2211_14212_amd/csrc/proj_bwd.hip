@@ -89,6 +89,10 @@ __global__ __launch_bounds__(256) void k_backward(const TP *__restrict__ proj, T
                                                   int tiles_y, int64_t groups, int pw_max, int ph_max,
                                                   int fp_angles, int *err_flag, Epilogue ep)
 {
+    // Angle chunk of this workgroup: all angles, or (small volumes) chunk
+    // blockIdx.y of gridDim.y, whose raw sums go to the partial volumes.
+    const int chunks = int(gridDim.y), chunk = int(blockIdx.y);
+    const int a_begin = int(int64_t(g.na) * chunk / chunks), a_end = int(int64_t(g.na) * (chunk + 1) / chunks);
     extern __shared__ __align__(16) unsigned char lds_raw[];
     double *cinv = reinterpret_cast<double *>(lds_raw);       // 2 * pw_max
     double *rinv = cinv + 2 * pw_max;                         // ph_max
@@ -131,7 +135,7 @@ __global__ __launch_bounds__(256) void k_backward(const TP *__restrict__ proj, T
     const float margin = 0.01f; // pixels; the exact FP64 intervals reject extra candidates
 
     // Tile footprints of every angle (or of the first fp_angles), computed once.
-    for (int a = threadIdx.x; a < fp_angles; a += 256) {
+    for (int a = a_begin + threadIdx.x; a < min(a_end, fp_angles); a += 256) {
         const Footprint f = tile_footprint(tab[a], g, tx0, tx1, ty0, ty1, tz0, tz1, margin);
         fps[a] = make_int4(f.iu_lo, f.iu_hi, f.iv_lo, f.iv_hi);
     }
@@ -145,7 +149,7 @@ __global__ __launch_bounds__(256) void k_backward(const TP *__restrict__ proj, T
     if constexpr (ACC_LDS)
         for (int kk = 0; kk < KZ; ++kk) accs[kk * 256 + threadIdx.x] = 0.f;
 
-    for (int a = 0; a < g.na; ++a) {
+    for (int a = a_begin; a < a_end; ++a) {
         const AngleGeo A = tab[a];
         Footprint f;
         if (a < fp_angles) {
@@ -297,6 +301,19 @@ __global__ __launch_bounds__(256) void k_backward(const TP *__restrict__ proj, T
         }
     }
 
+    if (chunks > 1) { // raw sums of this chunk's angles; k_bwd_combine finishes
+        if (valid) {
+            float *dst = ep.split + int64_t(chunk) * g.nx * g.ny * g.nz;
+#pragma unroll
+            for (int kk = 0; kk < KZ; ++kk) {
+                const int k = k0 + kk;
+                if (k < g.nz)
+                    dst[(int64_t(k) * g.ny + j) * g.nx + i] = ACC_LDS ? accs[kk * 256 + threadIdx.x]
+                                                                     : acc[ACC_LDS ? 0 : kk];
+            }
+        }
+        return;
+    }
     double part = 0.0;
     if (valid) {
 #pragma unroll
@@ -322,6 +339,45 @@ __global__ __launch_bounds__(256) void k_backward(const TP *__restrict__ proj, T
     }
 }
 
+// Sum of the angle chunks' partial volumes in chunk order, then the epilogue
+// of k_backward (out = c0 sum + c1 in1 + c2 in2 + c3 in3, partial sums of
+// out^2 per workgroup).
+template <typename TV>
+__global__ __launch_bounds__(256) void k_bwd_combine(const float *__restrict__ split, int chunks, int64_t n,
+                                                     TV *__restrict__ vol, Epilogue ep)
+{
+    __shared__ double red[4];
+    if (ep.scal && ep.scal[S_DONE] != 0.0) return;
+    double c0 = ep.c[0], c1 = ep.c[1], c2 = ep.c[2], c3 = ep.c[3];
+    if (ep.coef_idx >= 0) {
+        c0 = ep.scal[ep.coef_idx];
+        c1 = ep.scal[ep.coef_idx + 1];
+        c2 = ep.scal[ep.coef_idx + 2];
+        c3 = ep.scal[ep.coef_idx + 3];
+    }
+    double part = 0.0;
+    for (int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x; idx < n; idx += int64_t(gridDim.x) * 256) {
+        float a = 0.f;
+#pragma unroll 4
+        for (int c = 0; c < chunks; ++c) a += split[int64_t(c) * n + idx];
+        double o = c0 * double(a);
+        if (ep.in1 && c1 != 0.0) o += c1 * double(to_f32(static_cast<const TV *>(ep.in1)[idx]));
+        if (ep.in2 && c2 != 0.0) o += c2 * double(ep.in2[idx]);
+        if (ep.in3 && c3 != 0.0) o += c3 * double(to_f32(static_cast<const TV *>(ep.in3)[idx]));
+        const TV st = from_f32<TV>(float(o));
+        vol[idx] = st;
+        const double sv = double(to_f32(st));
+        part += sv * sv;
+    }
+    if (ep.partials) {
+        const double s = block_sum_256b(part, red);
+        if (threadIdx.x == 0) ep.partials[blockIdx.x] = s;
+    }
+}
+
+// One voxel per thread up to 2048 workgroups: the split volumes are small.
+int64_t combine_groups(int64_t n) { return std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 2048)); }
+
 struct BwdShape {
     int64_t tiles_x, tiles_y, tiles_z, groups;
 };
@@ -341,9 +397,32 @@ kct_status bwd_launch3(Plan &p, const void *proj, void *vol, const Epilogue &ep,
 {
     const BwdShape s = bwd_shape(p);
     const int64_t launch = ((s.groups + 7) / 8) * 8;
+    const int chunks = std::min(p.bwd_asplit, p.gp.na);
     // A dispatch holds fewer than 2^32 work-items (the runtime does not
     // report a larger grid, it truncates it).
-    if (launch * 256 >= (int64_t(1) << 32)) return fail(KCT_E_GEOMETRY, "back projection grid too large");
+    if (launch * 256 * chunks >= (int64_t(1) << 32)) return fail(KCT_E_GEOMETRY, "back projection grid too large");
+    if (chunks > 1) {
+        if (!ep.split) return fail(KCT_E_INVALID_ARG, "internal: angle-split back projection without a buffer");
+        Epilogue raw = ep; // the combine kernel applies the epilogue
+        raw.partials = nullptr;
+        const dim3 grid(static_cast<unsigned>(launch), static_cast<unsigned>(chunks), 1u);
+        if (p.bwd_acc_lds && KZ > 1)
+            hipLaunchKernelGGL((k_backward<TP, TV, KZ, NCM, true>), grid, dim3(256),
+                               p.bwd_lds + size_t(KZ) * 256 * sizeof(float), st, static_cast<const TP *>(proj),
+                               static_cast<TV *>(vol), p.d_tab, p.d_invv, p.gp, int(s.tiles_x), int(s.tiles_y),
+                               s.groups, p.bwd_pw, p.bwd_ph, p.bwd_fp_angles, p.d_err, raw);
+        else
+            hipLaunchKernelGGL((k_backward<TP, TV, KZ, NCM, false>), grid, dim3(256), p.bwd_lds, st,
+                               static_cast<const TP *>(proj), static_cast<TV *>(vol), p.d_tab, p.d_invv, p.gp,
+                               int(s.tiles_x), int(s.tiles_y), s.groups, p.bwd_pw, p.bwd_ph, p.bwd_fp_angles,
+                               p.d_err, raw);
+        const kct_status e = check_hip(hipGetLastError(), "back projection launch");
+        if (e != KCT_OK) return e;
+        const int64_t n = p.n_vox();
+        hipLaunchKernelGGL((k_bwd_combine<TV>), dim3(unsigned(combine_groups(n))), dim3(256), 0, st, ep.split,
+                           chunks, n, static_cast<TV *>(vol), ep);
+        return check_hip(hipGetLastError(), "back projection combine launch");
+    }
     if (p.bwd_acc_lds && KZ > 1) {
         hipLaunchKernelGGL((k_backward<TP, TV, KZ, NCM, true>), dim3(unsigned(launch)), dim3(256),
                            p.bwd_lds + size_t(KZ) * 256 * sizeof(float), st, static_cast<const TP *>(proj),
@@ -378,9 +457,35 @@ kct_status bwd_launch1(Plan &p, const void *proj, void *vol, const Epilogue &ep,
     return bwd_launch2<TP, TV, 1>(p, proj, vol, ep, st);
 }
 
+// Small volumes make too few tiles to fill 256 CUs (32^3: 128 workgroups);
+// their angles are then split over up to 16 chunks of workgroups whose
+// partial volumes a second kernel sums in chunk order.  KCT_BWD_SPLIT
+// (1..16) overrides the count.
+void choose_bwd_split(Plan &p)
+{
+    const GeoParams &g = p.gp;
+    const int64_t groups = bwd_shape(p).groups;
+    p.bwd_asplit = 1;
+    if (groups < 1024 && g.na > 1)
+        p.bwd_asplit = int(std::min<int64_t>({int64_t(16), int64_t(g.na), (2048 + groups - 1) / groups}));
+    if (const char *e = std::getenv("KCT_BWD_SPLIT")) {
+        const int v = std::atoi(e);
+        if (v >= 1 && v <= 16) p.bwd_asplit = std::min(v, g.na);
+    }
+}
+
 } // namespace
 
-int64_t bwd_num_groups(const Plan &p) { return bwd_shape(p).groups; }
+int64_t bwd_num_groups(const Plan &p)
+{
+    return std::min(p.bwd_asplit, p.gp.na) > 1 ? combine_groups(p.n_vox()) : bwd_shape(p).groups;
+}
+
+int64_t bwd_split_floats(const Plan &p)
+{
+    const int chunks = std::min(p.bwd_asplit, p.gp.na);
+    return chunks > 1 ? int64_t(chunks) * p.n_vox() : 0;
+}
 
 // Bounds that size the launch: the widest per-voxel footprint (columns) and
 // the largest per-tile detector patch, from the extreme magnification of the
@@ -436,7 +541,10 @@ kct_status choose_bwd_shape(Plan &p)
         p.bwd_ph = int(std::min<double>(ph, g.nv));
         p.bwd_lds = size_t(p.bwd_pw) * 16 + size_t(p.bwd_ph) * 8 + size_t(p.bwd_fp_angles) * 16 +
                     (size_t(p.bwd_pw) * p.bwd_ph + 8) * sizeof(float);
-        if (p.bwd_lds + size_t(p.bwd_kz) * 256 * sizeof(float) <= 64 * 1024) return KCT_OK;
+        if (p.bwd_lds + size_t(p.bwd_kz) * 256 * sizeof(float) <= 64 * 1024) {
+            choose_bwd_split(p);
+            return KCT_OK;
+        }
         if (p.bwd_fp_angles > 0) {
             p.bwd_fp_angles = 0;
             continue;

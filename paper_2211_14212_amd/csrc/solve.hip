@@ -51,7 +51,7 @@ constexpr size_t ALIGN = 256;
 size_t up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-    size_t scal = 0, pa = 0, pb = 0, pc = 0, stage = 0, gk = 0, work = 0, coef = 0, pad = 0;
+    size_t scal = 0, pa = 0, pb = 0, pc = 0, stage = 0, gk = 0, work = 0, coef = 0, pad = 0, bsplit = 0;
     size_t v[6] = {0, 0, 0, 0, 0, 0};
     size_t total = 0;
     int64_t nparts = 0;
@@ -143,6 +143,7 @@ Layout layout(const Plan &p, const kct_solve_params &prm)
     const bool expl = prm.flags & (KCT_FLAG_STOP_ON_RESIDUAL_INCREASE | KCT_FLAG_EXPLICIT_RESIDUAL);
     // The stop rule projects x itself (FP32), so its padded copy needs FP32.
     L.pad = o; o += up(size_t(2 * p.pad.vox) * (expl ? std::max<size_t>(vt, 4) : vt));
+    L.bsplit = o; o += up(sizeof(float) * size_t(bwd_split_floats(p))); // partial volumes (small volumes)
     const int k = prm.n_iter;
     switch (prm.solver) {
     case KCT_CGLS:
@@ -275,6 +276,14 @@ Reduced red(const kct_state &s, const double *parts, int64_t n, int slot)
     return reduce_for_scalar(parts, n, s.stage(slot), s.st);
 }
 
+// The back projector with this state's partial-volume buffer (used when the
+// plan splits the angles of a small volume over several workgroups).
+kct_status backward_into(kct_state &s, Plan &p, const void *proj, int pdt, void *vol, int vdt, Epilogue ep)
+{
+    ep.split = reinterpret_cast<float *>(s.ws + s.L.bsplit);
+    return launch_backward(p, proj, pdt, vol, vdt, ep, s.st);
+}
+
 kct_status forward_into(kct_state &s, const void *vol, void *proj, const Epilogue &ep)
 {
     Plan &p = *s.plan;
@@ -290,7 +299,7 @@ kct_status cgls_init(kct_state &s)
     KCT_TRY(vk_scale(s.b, KCT_F32, s.v(0), s.vt(), s.N(), nullptr, -1, nullptr, s.st)); // r = b
     Epilogue ep;
     ep.partials = s.pa();
-    KCT_TRY(launch_backward(p, s.v(0), s.vt(), s.v(2), s.vt(), ep, s.st)); // p = A^T r
+    KCT_TRY(backward_into(s, p, s.v(0), s.vt(), s.v(2), s.vt(), ep)); // p = A^T r
     return sk_cgls_init(s.S(), red(s, s.pa(), bwd_num_groups(p), 0), s.prm.lambda, s.prm.n_iter, s.st);
 }
 
@@ -316,7 +325,7 @@ kct_status cgls_iter(kct_state &s)
         eb.in2 = s.x;
         eb.in3 = s.v(2);
     }
-    KCT_TRY(launch_backward(p, s.v(0), s.vt(), s.v(3), s.vt(), eb, s.st)); // s = A^T r - lam^2 x'
+    KCT_TRY(backward_into(s, p, s.v(0), s.vt(), s.v(3), s.vt(), eb)); // s = A^T r - lam^2 x'
     KCT_TRY(sk_cgls_beta(s.S(), red(s, s.pa(), bwd_num_groups(p), 0), red(s, s.pb(), vk_groups(s.N()), 2),
                          s.hist, s.st));
     return vk_cgls_vol(s.x, s.v(2), s.v(3), s.vt(), s.M(), s.S(), s.pc(), s.st);
@@ -335,7 +344,7 @@ kct_status gk_init(kct_state &s, void *V, double *gk)
     eb.scal = s.S();
     eb.coef_idx = S_B0; // V = A^T U / beta_1
     eb.partials = s.pa();
-    KCT_TRY(launch_backward(p, s.v(0), s.vt(), V, s.vt(), eb, s.st));
+    KCT_TRY(backward_into(s, p, s.v(0), s.vt(), V, s.vt(), eb));
     return sk_gk_init2(s.S(), red(s, s.pa(), bwd_num_groups(p), 0), gk, s.st);
 }
 
@@ -355,7 +364,7 @@ kct_status gk_step(kct_state &s, void *V_in, void *V_out)
     eb.coef_idx = S_B0;
     eb.in1 = V_in;
     eb.partials = s.pa();
-    return launch_backward(p, s.v(0), s.vt(), V_out, s.vt(), eb, s.st);
+    return backward_into(s, p, s.v(0), s.vt(), V_out, s.vt(), eb);
 }
 
 kct_status lsqr_init(kct_state &s)
@@ -443,7 +452,7 @@ kct_status irn_begin_outer(kct_state &s, int outer)
         KCT_TRY(vk_fill(tv_r2(s), KCT_F32, 3 * s.M(), 0.f, s.st));
     }
     Epilogue eb;
-    KCT_TRY(launch_backward(p, s.v(0), s.vt(), s.v(3), s.vt(), eb, s.st)); // s = A^T r1
+    KCT_TRY(backward_into(s, p, s.v(0), s.vt(), s.v(3), s.vt(), eb)); // s = A^T r1
     KCT_TRY(tv_adjoint_add(p, s.v(3), s.vt(), tv_r2(s), tv_w(s), lam, nullptr, s.pa(), s.st));
     KCT_TRY(vk_scale(s.v(3), s.vt(), s.v(2), s.vt(), s.M(), nullptr, -1, nullptr, s.st)); // p = s
     return sk_tv_restart(s.S(), red(s, s.pa(), tv_num_groups(s.M()), 0), outer == 0, s.total, s.prm.lambda, s.st);
@@ -470,7 +479,7 @@ kct_status irn_iter(kct_state &s)
     KCT_TRY(tv_grad_store(p, s.v(2), s.vt(), tv_w(s), tv_r2(s), s.S(), S_V3, 0.0, true, s.st)); // r2
     Epilogue eb;
     eb.scal = s.S();
-    KCT_TRY(launch_backward(p, s.v(0), s.vt(), s.v(3), s.vt(), eb, s.st)); // s = A^T r1
+    KCT_TRY(backward_into(s, p, s.v(0), s.vt(), s.v(3), s.vt(), eb)); // s = A^T r1
     KCT_TRY(tv_adjoint_add(p, s.v(3), s.vt(), tv_r2(s), tv_w(s), lam, s.S(), s.pa(), s.st));
     KCT_TRY(sk_cgls_beta(s.S(), red(s, s.pa(), tv_num_groups(s.M()), 0), red(s, s.pc(), vk_groups(s.N()), 2),
                          s.hist, s.st));
@@ -495,7 +504,7 @@ void *gm_V(kct_state &s, int i) { return static_cast<char *>(s.v(0)) + size_t(i)
 kct_status apply_B(kct_state &s, const void *proj, int pdt, void *vol, int vdt, const Epilogue &ep)
 {
     if (s.prm.backprojector == KCT_BP_INTERP) return launch_interp_backward(*s.plan, proj, pdt, vol, vdt, ep, s.st);
-    return launch_backward(*s.plan, proj, pdt, vol, vdt, ep, s.st);
+    return backward_into(s, *s.plan, proj, pdt, vol, vdt, ep);
 }
 
 int64_t B_groups(const kct_state &s)
@@ -604,7 +613,7 @@ kct_status sa_init(kct_state &s)
     // V_k = 1 / (A_k^T 1).
     KCT_TRY(vk_fill(sa_r(s), KCT_F32, s.N(), 1.f, s.st));
     for (int k = 0; k < m; ++k)
-        KCT_TRY(launch_backward(s.sub[k], sa_r(s) + sa_off(s, k), KCT_F32, sa_V(s, k), KCT_F32, plain, s.st));
+        KCT_TRY(backward_into(s, s.sub[k], sa_r(s) + sa_off(s, k), KCT_F32, sa_V(s, k), KCT_F32, plain));
     KCT_TRY(sa_inv_nz(sa_V(s, 0), int64_t(m) * s.M(), s.st));
     KCT_TRY(vk_fill(s.x, KCT_F32, s.M(), 0.f, s.st));
     return sa_sc_init(s.S(), s.prm.n_iter, s.prm.lambda, s.st);
@@ -629,7 +638,7 @@ kct_status sa_iter(kct_state &s)
         KCT_TRY(sa_sc_res(s.S(), rr.ptr, rr.n, s.hist, k == 0, k == m - 1, s.st));
         KCT_TRY(sa_mul(r, sa_W(s) + sa_off(s, k), nk, s.st));
         Epilogue plain;
-        KCT_TRY(launch_backward(v, r, KCT_F32, sa_v(s), KCT_F32, plain, s.st));
+        KCT_TRY(backward_into(s, v, r, KCT_F32, sa_v(s), KCT_F32, plain));
         KCT_TRY(sa_update_x(s.x, sa_v(s), sa_V(s, k), s.M(), s.S(), s.st));
     }
     return KCT_OK;
@@ -661,7 +670,7 @@ kct_status fl_init(kct_state &s)
     KCT_TRY(fl_sc_init(s.S(), rca, red(s, s.pb(), gm_num_groups(N), 1), s.prm.n_iter, s.prm.lambda, s.st));
     KCT_TRY(fl_fill_s(s.x, M, s.S(), S_FL_C0, s.st)); // x = x0
     Epilogue eb;
-    KCT_TRY(launch_backward(p, a, KCT_F32, fl_g(s), KCT_F32, eb, s.st)); // g = A^T a
+    KCT_TRY(backward_into(s, p, a, KCT_F32, fl_g(s), KCT_F32, eb)); // g = A^T a
     KCT_TRY(fl_bbar(fl_U(s, 0), s.b, a, N, s.S(), s.pa(), s.st));        // bbar = b - c0 a -> ||bbar||^2
     KCT_TRY(fl_sc_beta1(s.S(), red(s, s.pa(), fl_groups(N), 0), s.st));
     return gm_scale(fl_U(s, 0), KCT_F32, N, s.S(), S_V0, s.st);
@@ -699,7 +708,7 @@ kct_status fl_iter(kct_state &s)
     else KCT_TRY(tv_weights(p, s.x, fl_w(s), s.prm.tv_eps, s.st));
     // v = P^T A^T u_k = L D K^+ E^T A^T u_k.
     Epilogue eb;
-    KCT_TRY(launch_backward(p, fl_U(s, k), KCT_F32, r, KCT_F32, eb, s.st));
+    KCT_TRY(backward_into(s, p, fl_U(s, k), KCT_F32, r, KCT_F32, eb));
     KCT_TRY(fl_sum(r, M, s.pa(), s.st));
     KCT_TRY(fl_sc_ecoef(s.S(), red(s, s.pa(), fl_groups(M), 0), S_FL_E, s.st));
     KCT_TRY(fl_axpy_sum(r, fl_g(s), M, s.S(), S_FL_E, s.pa(), s.pb(), s.st));
