@@ -258,7 +258,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU angle-sharded "
-              "path is a design in DESIGN.md, not built", file=sys.stderr)
+              "path is a documented design, not built", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
