@@ -248,6 +248,13 @@ typedef struct kct_solve_params {
  * Implied by KCT_FLAG_STOP_ON_RESIDUAL_INCREASE. */
 #define KCT_FLAG_EXPLICIT_RESIDUAL 2u
 
+/* Warm start: d_x holds x_0 on entry instead of being overwritten with 0
+ * (CGLS, with or without damping; LSQR and LSMR with lambda = 0, which then
+ * run on b - A x_0 and add their iterates to x_0; SIRT and OS-SART).  A
+ * stationary method (SIRT, OS-SART) started from its own k-th iterate
+ * continues its run exactly; a Krylov method starts a new Krylov space. */
+#define KCT_FLAG_X0_GIVEN 4u
+
 /* Workspace bytes kct_solve needs for `params` on `plan`. */
 kct_status kct_solve_workspace_bytes(const kct_plan *plan, const kct_solve_params *params,
                                      size_t *bytes);

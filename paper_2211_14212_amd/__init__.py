@@ -103,12 +103,13 @@ BACKPROJECTORS = {"matched": _lib.KCT_BP_MATCHED, "interp": _lib.KCT_BP_INTERP}
 
 def _params(solver, n_iter, lam, vec_dtype, tv_outer=0, tv_inner=0, tv_eps=1e-3, lam_rule="fixed",
             noise_level=0.0, backprojector="matched", n_subsets=0, stop_on_residual_increase=False,
-            explicit_residual=False):
+            explicit_residual=False, warm_start=False):
     code = SOLVERS[solver] if isinstance(solver, str) else int(solver)
     rule = LAMBDA_RULES[lam_rule] if isinstance(lam_rule, str) else int(lam_rule)
     bp = BACKPROJECTORS[backprojector] if isinstance(backprojector, str) else int(backprojector)
     flags = ((_lib.KCT_FLAG_STOP_ON_RESIDUAL_INCREASE if stop_on_residual_increase else 0)
-             | (_lib.KCT_FLAG_EXPLICIT_RESIDUAL if explicit_residual else 0))
+             | (_lib.KCT_FLAG_EXPLICIT_RESIDUAL if explicit_residual else 0)
+             | (_lib.KCT_FLAG_X0_GIVEN if warm_start else 0))
     return _lib.KctSolveParams(code, int(n_iter), float(lam), int(tv_outer), int(tv_inner), float(tv_eps),
                                dtype_code(vec_dtype), rule, float(noise_level), bp, int(n_subsets), flags, 0)
 
@@ -216,7 +217,8 @@ class Plan:
         ("fixed", "gcv" or "dp") and noise_level (hybrid LSQR, fLSQR-TV); backprojector
         ("matched" or "interp", AB-/BA-GMRES); n_subsets (OS-SART; lam is
         the relaxation of SIRT and OS-SART); stop_on_residual_increase and
-        explicit_residual (CGLS, LSQR, LSMR).  history is an
+        explicit_residual (CGLS, LSQR, LSMR); warm_start (x holds x0: CGLS,
+        undamped LSQR/LSMR, SIRT, OS-SART).  history is an
         (n_rows, KCT_HIST_COLS) float64 device tensor or None.  The call only
         enqueues work on the stream.
         """
@@ -224,6 +226,8 @@ class Plan:
         if b.dtype != torch.float32:
             raise TypeError("b must be float32")
         if x is None:
+            if tv.get("warm_start"):
+                raise ValueError("warm_start needs x (it holds x0)")
             x = torch.empty(self.geom.vol_shape, dtype=torch.float32, device=self.device)
         self._check(x, self.geom.vol_shape, "x")
         p = _params(solver, n_iter, lam, vec_dtype, **tv)

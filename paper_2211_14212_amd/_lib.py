@@ -26,6 +26,7 @@ KCT_BP_MATCHED, KCT_BP_INTERP = 0, 1
 # flags
 KCT_FLAG_STOP_ON_RESIDUAL_INCREASE = 1
 KCT_FLAG_EXPLICIT_RESIDUAL = 2
+KCT_FLAG_X0_GIVEN = 4
 KCT_HIST_COLS = 5
 # kct_lambda_rule
 KCT_LAMBDA_FIXED, KCT_LAMBDA_GCV, KCT_LAMBDA_DP = 0, 1, 2

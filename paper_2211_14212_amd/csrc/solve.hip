@@ -87,10 +87,18 @@ kct_status check_params(const kct_solve_params *prm)
         if (!is_gmres(prm->solver))
             return fail(KCT_E_INVALID_ARG, "only AB- and BA-GMRES take an unmatched back projector");
     }
-    if (prm->flags & ~(KCT_FLAG_STOP_ON_RESIDUAL_INCREASE | KCT_FLAG_EXPLICIT_RESIDUAL))
+    if (prm->flags & ~(KCT_FLAG_STOP_ON_RESIDUAL_INCREASE | KCT_FLAG_EXPLICIT_RESIDUAL | KCT_FLAG_X0_GIVEN))
         return fail(KCT_E_INVALID_ARG, "unknown flags");
+    if (prm->flags & KCT_FLAG_X0_GIVEN) {
+        const int sv = prm->solver;
+        if (sv != KCT_CGLS && sv != KCT_LSQR && sv != KCT_LSMR && !is_sart(sv))
+            return fail(KCT_E_INVALID_ARG, "a given x0 is for CGLS, LSQR, LSMR, SIRT and OS-SART");
+        if ((sv == KCT_LSQR || sv == KCT_LSMR) && prm->lambda != 0.0)
+            return fail(KCT_E_INVALID_ARG, "LSQR and LSMR start from a given x0 only without damping");
+    }
     if (prm->reserved != 0) return fail(KCT_E_INVALID_ARG, "reserved must be 0");
-    if (prm->flags && prm->solver != KCT_CGLS && prm->solver != KCT_LSQR &&
+    if ((prm->flags & (KCT_FLAG_STOP_ON_RESIDUAL_INCREASE | KCT_FLAG_EXPLICIT_RESIDUAL)) &&
+        prm->solver != KCT_CGLS && prm->solver != KCT_LSQR &&
         prm->solver != KCT_LSMR)
         return fail(KCT_E_INVALID_ARG, "explicit residuals and the stop rule are for CGLS, LSQR and LSMR");
     if (is_sart(prm->solver)) {
@@ -292,13 +300,35 @@ kct_status forward_into(kct_state &s, const void *vol, void *proj, const Epilogu
 }
 
 // ---------------------------------------------------------------- CGLS
+bool x0_given(const kct_state &s) { return s.prm.flags & KCT_FLAG_X0_GIVEN; }
+
+// r = b - A x (x FP32; its padded copy in vector storage), in place on r = b.
+kct_status residual_from_x(kct_state &s, void *r, double *partials)
+{
+    Plan &p = *s.plan;
+    KCT_TRY(launch_pad_volume_as(p, s.x, KCT_F32, s.vt(), s.pad(), s.st));
+    Epilogue ef;
+    ef.c[0] = -1.0;
+    ef.c[1] = 1.0;
+    ef.in1 = r;
+    ef.partials = partials;
+    return launch_forward(p, s.pad(), s.vt(), r, s.vt(), ef, s.st);
+}
+
 kct_status cgls_init(kct_state &s)
 {
     Plan &p = *s.plan;
-    KCT_TRY(vk_fill(s.x, KCT_F32, s.M(), 0.f, s.st));
+    if (!x0_given(s)) KCT_TRY(vk_fill(s.x, KCT_F32, s.M(), 0.f, s.st));
     KCT_TRY(vk_scale(s.b, KCT_F32, s.v(0), s.vt(), s.N(), nullptr, -1, nullptr, s.st)); // r = b
     Epilogue ep;
     ep.partials = s.pa();
+    if (x0_given(s)) { // r = b - A x0, s = A^T r - lam^2 x0
+        KCT_TRY(residual_from_x(s, s.v(0), nullptr));
+        if (s.prm.lambda != 0.0) {
+            ep.c[2] = -s.prm.lambda * s.prm.lambda;
+            ep.in2 = s.x;
+        }
+    }
     KCT_TRY(backward_into(s, p, s.v(0), s.vt(), s.v(2), s.vt(), ep)); // p = A^T r
     return sk_cgls_init(s.S(), red(s, s.pa(), bwd_num_groups(p), 0), s.prm.lambda, s.prm.n_iter, s.st);
 }
@@ -335,11 +365,14 @@ kct_status cgls_iter(kct_state &s)
 kct_status gk_init(kct_state &s, void *V, double *gk)
 {
     Plan &p = *s.plan;
-    KCT_TRY(vk_fill(s.x, KCT_F32, s.M(), 0.f, s.st));
-    KCT_TRY(vk_scale(s.b, KCT_F32, s.v(0), s.vt(), s.N(), nullptr, -1, s.pa(), s.st)); // U = b
+    const bool x0 = x0_given(s); // LSQR / LSMR without damping: Golub-Kahan from b - A x0
+    if (!x0) KCT_TRY(vk_fill(s.x, KCT_F32, s.M(), 0.f, s.st));
+    KCT_TRY(vk_scale(s.b, KCT_F32, s.v(0), s.vt(), s.N(), nullptr, -1, x0 ? nullptr : s.pa(), s.st)); // U = b
+    if (x0) KCT_TRY(residual_from_x(s, s.v(0), s.pa())); // U = b - A x0
+    const Reduced ru = red(s, s.pa(), x0 ? fwd_num_groups(p) : vk_groups(s.N()), 0);
     // LSQR's damping; hybrid LSQR with a lambda rule recurs undamped quantities.
     const double lam = s.prm.lambda_rule == KCT_LAMBDA_FIXED ? s.prm.lambda : 0.0;
-    KCT_TRY(sk_gk_init1(s.S(), red(s, s.pa(), vk_groups(s.N()), 0), lam, s.prm.n_iter, s.st));
+    KCT_TRY(sk_gk_init1(s.S(), ru, lam, s.prm.n_iter, s.st));
     Epilogue eb;
     eb.scal = s.S();
     eb.coef_idx = S_B0; // V = A^T U / beta_1
@@ -615,7 +648,7 @@ kct_status sa_init(kct_state &s)
     for (int k = 0; k < m; ++k)
         KCT_TRY(backward_into(s, s.sub[k], sa_r(s) + sa_off(s, k), KCT_F32, sa_V(s, k), KCT_F32, plain));
     KCT_TRY(sa_inv_nz(sa_V(s, 0), int64_t(m) * s.M(), s.st));
-    KCT_TRY(vk_fill(s.x, KCT_F32, s.M(), 0.f, s.st));
+    if (!x0_given(s)) KCT_TRY(vk_fill(s.x, KCT_F32, s.M(), 0.f, s.st));
     return sa_sc_init(s.S(), s.prm.n_iter, s.prm.lambda, s.st);
 }
 

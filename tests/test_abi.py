@@ -55,6 +55,7 @@ def test_header_constants_match_binding():
     assert int(re.search(r"#define KCT_FLAG_STOP_ON_RESIDUAL_INCREASE (\d+)u", src).group(1)) == \
         _lib.KCT_FLAG_STOP_ON_RESIDUAL_INCREASE
     assert int(re.search(r"#define KCT_FLAG_EXPLICIT_RESIDUAL (\d+)u", src).group(1)) == _lib.KCT_FLAG_EXPLICIT_RESIDUAL
+    assert int(re.search(r"#define KCT_FLAG_X0_GIVEN (\d+)u", src).group(1)) == _lib.KCT_FLAG_X0_GIVEN
 
 
 def test_status_strings_and_version():

@@ -205,3 +205,54 @@ def test_checkpoint_resume_bitwise(kct, solver, kw, k):
     bad = dict(ckpt, iters=total + 1)
     with pytest.raises(kct._lib.KctError):
         plan2.resume_state(bt, bad)
+
+
+@pytest.mark.parametrize("solver,lam", [("cgls", 0.0), ("cgls", 20.0), ("lsqr", 0.0), ("lsmr", 0.0)])
+def test_warm_start_matches_oracle(kct, solver, lam):
+    """KCT_FLAG_X0_GIVEN: CGLS from x0 against the oracle's CGLS from x0
+    (damped too); undamped LSQR / LSMR from x0 are x0 plus the method on
+    b - A x0.  Same gate as the cold-start parity tests."""
+    og, kg, b = _problem("cgls32")
+    plan = kct.Plan(kg)
+    x0 = synth.random_volume(kg.vol_shape, 11).astype(np.float32)
+    n = 8
+    x = torch.from_numpy(x0.copy()).to(DEV)
+    x, h = plan.solve(torch.from_numpy(b).to(DEV), solver, n, lam, x=x, warm_start=True)
+    torch.cuda.synchronize()
+    A, AT = (lambda v: oracle.forward(og, v)), (lambda y: oracle.adjoint(og, y))
+    b64, x064 = b.astype(np.float64), x0.astype(np.float64)
+    if solver == "cgls":
+        ref, _ = S.cgls(A, AT, b64, n, lam, x0=x064)
+    else:
+        d, _ = getattr(S, solver)(A, AT, b64 - A(x064), n)
+        ref = x064 + d
+    err = _rel(x.cpu().numpy(), ref)
+    print(f"[warm {solver} lam={lam}] rel err {err:.2e}", flush=True)
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("solver,kw", [("sirt", {}), ("os_sart", {"n_subsets": 4})])
+def test_warm_start_continues_stationary_methods(kct, solver, kw):
+    """SIRT / OS-SART are stationary: 4 iterations, then 6 more from that
+    iterate, are bitwise 10 straight iterations."""
+    og, kg, b = _problem("cgls32")
+    plan = kct.Plan(kg)
+    bt = torch.from_numpy(b).to(DEV)
+    x4, _ = plan.solve(bt, solver, 4, 1.0, **kw)
+    x10, _ = plan.solve(bt, solver, 6, 1.0, x=x4.clone(), warm_start=True, **kw)
+    ref, _ = plan.solve(bt, solver, 10, 1.0, **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(x10, ref)
+
+
+def test_warm_start_rejected_where_it_does_not_apply(kct):
+    og, kg, b = _problem("cgls32")
+    plan = kct.Plan(kg)
+    bt = torch.from_numpy(b).to(DEV)
+    x = torch.zeros(kg.vol_shape, device=DEV)
+    for solver, lam, kw in (("lsqr", 1.0, {}), ("hybrid_lsqr", 0.5, {}), ("ab_gmres", 0.0, {}),
+                            ("irn_tv_cgls", 0.5, dict(tv_outer=1, tv_inner=2))):
+        with pytest.raises(kct._lib.KctError):
+            plan.solve(bt, solver, 3, lam, x=x, warm_start=True, **kw)
+    with pytest.raises(ValueError):
+        plan.solve(bt, "cgls", 3, warm_start=True)

@@ -91,7 +91,7 @@ def test_rule_rejected_where_it_does_not_apply(kct):
         with pytest.raises(kct._lib.KctError):
             plan.solve(bt, solver, 3, lam, stop_on_residual_increase=True, **kw)
     lib = kct._lib.load()
-    for flags, reserved in ((4, 0), (1, 7)):
+    for flags, reserved in ((8, 0), (1, 7)):
         p = kct._lib.KctSolveParams(kct._lib.KCT_CGLS, 3, 0.0, 0, 0, 1e-3, 0, 0, 0.0, 0, 0, flags, reserved)
         n = ctypes.c_size_t()
         assert lib.kct_solve_workspace_bytes(plan.handle, ctypes.byref(p), ctypes.byref(n)) != 0
