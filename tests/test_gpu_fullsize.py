@@ -99,3 +99,45 @@ def test_full_size_muct1500_blocks(kct):
         assert np.count_nonzero(refb) > 100
         assert _rel(gotb, refb) <= 1e-6
     assert kct._lib.load().kct_debug_take_error_flag(plan.handle) == 0
+
+
+def test_full_size_solver_identities(kct):
+    """Solver parity at the benchmark's and the torso's full sizes, through
+    identities that hold at any size (the oracle would need minutes per
+    product here):
+    - 256^3 / 360 x 512^2 (the benchmark's launch configuration): CGLS and
+      LSQR produce the same iterates in exact arithmetic (Sec. 2.1.2), and
+      CGLS's recurred residual equals the explicit ||b - A x_k||;
+    - 512^3 / 720 x 1024 x 768: hybrid LSQR with a fixed lambda equals damped
+      LSQR (Sec. 2.2.1) iterate by iterate.
+    Gates: 1e-5 relative (the FP32 rounding of 10 iterations)."""
+    gd = synth.geometry("medical256")
+    plan = kct.Plan(kct.Geometry.from_dict(gd))
+    print("[full medical256] phantom, projections, CGLS-10 and LSQR-10", flush=True)
+    xt = torch.from_numpy(synth.phantom("medical256")).to(DEV)
+    b, _ = synth.add_noise_torch(plan.forward(xt), synth.WORKLOADS["medical256"]["noise"], 2)
+    xc, hc = plan.solve(b, "cgls", 10)
+    xl, hl = plan.solve(b, "lsqr", 10)
+    r = torch.linalg.vector_norm((plan.forward(xc) - b).double())
+    torch.cuda.synchronize()
+    d = float(torch.linalg.vector_norm(xc - xl) / torch.linalg.vector_norm(xc))
+    print(f"[full medical256] CGLS vs LSQR {d:.2e}; recurred {float(hc[-1, 0]):.6e} explicit {float(r):.6e}",
+          flush=True)
+    assert d <= 1e-5
+    assert abs(float(hc[-1, 0]) - float(r)) <= 1e-5 * float(r)
+    np.testing.assert_allclose(hc[:, 0].cpu().numpy(), hl[:, 0].cpu().numpy(), rtol=1e-5)
+    del xt, b, xc, xl, plan
+    torch.cuda.empty_cache()
+
+    gd = synth.geometry("torso512")
+    plan = kct.Plan(kct.Geometry.from_dict(gd))
+    print("[full torso512] random volume, projections, LSQR-10 and hybrid LSQR-10 at lambda 10", flush=True)
+    x = torch.from_numpy(synth.random_volume(plan.geom.vol_shape, 33)).to(DEV)
+    b = plan.forward(x)
+    del x
+    xd, hd = plan.solve(b, "lsqr", 10, 10.0)
+    xh, hh = plan.solve(b, "hybrid_lsqr", 10, 10.0)
+    torch.cuda.synchronize()
+    d = float(torch.linalg.vector_norm(xd - xh) / torch.linalg.vector_norm(xd))
+    print(f"[full torso512] damped LSQR vs hybrid {d:.2e}", flush=True)
+    assert d <= 1e-5
