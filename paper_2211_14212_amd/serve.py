@@ -9,6 +9,10 @@ so kernels of different requests overlap on the GPU.  A request leaves when
 its last iteration has run on the device; its memory is freed and queued
 requests are admitted in its place.  Each request's result is bitwise the
 same as a solo kct_solve of it (deterministic kernels, private buffers).
+Admission is first-come first-served by default; ``policy="sjf"`` admits the
+queued request with the least work first (ray-iterations, the cost of its
+projector calls), which shortens typical latency when the stream outruns
+the GPU, at the expense of the largest requests.
 A request can be cancelled (``Server.cancel``): no further iteration of it is
 enqueued, and once its last enqueued one has run its memory is freed and it
 returns a result marked ``cancelled`` with no image.  The other requests are
@@ -18,7 +22,7 @@ Latency = completion time - arrival time.  The serial baseline runs the same
 stream through the plain per-request path (one kct_solve at a time, FIFO).
 
 CLI:  python -m paper_2211_14212_amd.serve [--requests 64] [--rate 2.0]
-          [--size-scale 1.0] [--budget-gb 200] [--serial]
+          [--size-scale 1.0] [--budget-gb 200] [--no-serial] [--sjf]
 """
 from __future__ import annotations
 
@@ -72,6 +76,11 @@ class _Active:
         self.enqueued = 0
 
 
+def request_work(req: Request) -> int:
+    """Ray-iterations of a request: the size of its projector calls."""
+    return req.n_iter * req.geom.n_rays
+
+
 def request_bytes(plan: Plan, req: Request) -> int:
     """Device bytes a request holds while active."""
     ws = plan.workspace_bytes(req.solver, req.n_iter, req.lam, req.vec_dtype)
@@ -82,7 +91,10 @@ def request_bytes(plan: Plan, req: Request) -> int:
 
 class Server:
     def __init__(self, budget_bytes: float = 200e9, device: int = 0, max_active: int = 16,
-                 keep_results: bool = True, verbose: bool = False):
+                 keep_results: bool = True, verbose: bool = False, policy: str = "fifo"):
+        if policy not in ("fifo", "sjf"):
+            raise ValueError(policy)
+        self.policy = policy
         self.budget = int(budget_bytes)
         self.device = torch.device("cuda", device)
         self.max_active = max_active
@@ -114,19 +126,26 @@ class Server:
                 while pending and pending[0].arrival <= now:
                     queue.append(pending.popleft())
                 # Cancelled requests still waiting leave at once.
-                for req in [q for q in queue if q.id in self._cancel]:
-                    queue.remove(req)
-                    results[req.id] = Result(req.id, req.arrival, now, now, None, None, cancelled=True)
-                    self.log.append(("cancel", req.id, now, used))
-                # Admission: FIFO while the head fits the budget.
+                if any(q.id in self._cancel for q in queue):
+                    keep: deque[Request] = deque()
+                    for req in queue:
+                        if req.id in self._cancel:
+                            results[req.id] = Result(req.id, req.arrival, now, now, None, None, cancelled=True)
+                            self.log.append(("cancel", req.id, now, used))
+                        else:
+                            keep.append(req)
+                    queue = keep
+                # Admission while the next request fits the budget: the head
+                # of the queue (FIFO) or the least work (SJF, ties by arrival).
                 while queue and len(active) < self.max_active:
-                    req = queue[0]
+                    i = 0 if self.policy == "fifo" else min(range(len(queue)), key=lambda k: request_work(queue[k]))
+                    req = queue[i]
                     plan = Plan(req.geom, self.device.index)
                     need = request_bytes(plan, req)
                     if used + need > self.budget and active:
                         plan.close()
                         break
-                    queue.popleft()
+                    del queue[i]
                     stream = torch.cuda.Stream(device=self.device)
                     state = plan.state(req.b, req.solver, req.n_iter, req.lam, req.vec_dtype, stream=stream)
                     used += need
@@ -263,6 +282,7 @@ def main(argv=None):
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--max-active", type=int, default=16)
     ap.add_argument("--no-serial", action="store_true")
+    ap.add_argument("--sjf", action="store_true", help="also serve the stream with shortest-job-first admission")
     args = ap.parse_args(argv)
     print("[serve] generating requests", file=sys.stderr, flush=True)
     reqs = make_requests(args.requests, args.rate, size_scale=args.size_scale)
@@ -272,6 +292,11 @@ def main(argv=None):
     res = srv.run(reqs)
     out = {"batched": summarize(res)}
     print(f"[serve] batched {out['batched']}", file=sys.stderr, flush=True)
+    if args.sjf:
+        sjf = Server(args.budget_gb * 1e9, max_active=args.max_active, keep_results=False, verbose=True,
+                     policy="sjf").run(reqs)
+        out["batched_sjf"] = summarize(sjf)
+        print(f"[serve] batched, shortest job first {out['batched_sjf']}", file=sys.stderr, flush=True)
     if not args.no_serial:
         ser = serve_serial(reqs, keep_results=False, verbose=True)
         out["serial"] = summarize(ser)

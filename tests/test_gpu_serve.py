@@ -40,6 +40,22 @@ def test_mix_equals_alone(stream):
     assert s["p99_s"] >= s["p50_s"] > 0
 
 
+def test_sjf_admission_results_bitwise(stream):
+    """Shortest-job-first admission changes the order, not the results."""
+    serve, reqs = stream
+    srv = serve.Server(budget_bytes=50e9, max_active=3, policy="sjf")
+    res = srv.run(reqs)
+    assert len(res) == len(reqs) and not any(r.cancelled for r in res)
+    for req, r in zip(reqs, res):
+        plan = serve.Plan(req.geom)
+        x, h = plan.solve(req.b, req.solver, req.n_iter, req.lam)
+        torch.cuda.synchronize()
+        assert torch.equal(r.x, x), req.id
+        assert torch.equal(r.history, h), req.id
+    admits = [e[1] for e in srv.log if e[0] == "admit"]
+    assert sorted(admits) == sorted(r.id for r in reqs)
+
+
 def test_budget_respected(stream):
     serve, reqs = stream
     plans = [serve.Plan(r.geom) for r in reqs]
