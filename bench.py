@@ -233,7 +233,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--reps", type=int, default=5, help="calls per projector timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-solves", action="store_true")
+    ap.add_argument("--no-solves", action="store_true", help="skip the solves (with --operators-only: the IRN-TV run)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--workload", default=WORKLOAD, help="synthetic workload (default: the benchmark's)")
     ap.add_argument("--vec-dtype", default="f32", choices=sorted(DTYPES),
@@ -282,13 +282,21 @@ def main():
         stats = {"rays": kg.n_rays, "voxels": kg.n_voxels, "voxel_views": kg.n_voxels * len(kg.angles),
                  "nnz": None, "hit_rays": None}
 
-    log(f"[bench] phantom ({wl})")
-    x_true = big_phantom if big_phantom is not None else synth.phantom(wl)
     plan = kct.Plan(kg)
-    xt = torch.from_numpy(x_true).to(dev)
+    if args.profile_kernels and synth.WORKLOADS[wl]["phantom"]["kind"] == "porous":
+        # The projectors' memory traffic does not depend on the values: a
+        # seeded uniform volume stands in for the slow porous phantom.
+        log(f"[bench] uniform random volume ({wl})")
+        xt = torch.rand(kg.vol_shape, device=dev, generator=torch.Generator(device=dev).manual_seed(4))
+    else:
+        log(f"[bench] phantom ({wl})")
+        x_true = big_phantom if big_phantom is not None else synth.phantom(wl)
+        xt = torch.from_numpy(x_true).to(dev)
     if args.profile_kernels:
-        y = torch.empty(kg.proj_shape, device=dev)
-        xb = torch.empty(kg.vol_shape, device=dev)
+        # Projector inputs and outputs in the --vec-dtype storage.
+        xt = xt.to(vdt)
+        y = torch.empty(kg.proj_shape, device=dev, dtype=vdt)
+        xb = torch.empty(kg.vol_shape, device=dev, dtype=vdt)
         src = torch.ones(1 << 28, device=dev)  # 1 GiB of FP32
         dst = torch.empty_like(src)
         for _ in range(args.reps):
@@ -339,7 +347,7 @@ def main():
                "bwd_gvoxel_views_per_s": round(kg.n_voxels * len(kg.angles) / (bwd_ms / 1000.0) / 1e9, 3)}
         if stats.get("nnz"):
             rep["gsegments_per_s"] = round(stats["nnz"] / (fwd_ms / 1000.0) / 1e9, 2)
-        if "n_outer" in sol:
+        if "n_outer" in sol and not args.no_solves:
             inner = 2
             torch.cuda.synchronize()
             t0 = time.perf_counter()

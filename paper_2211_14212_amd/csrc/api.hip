@@ -170,6 +170,16 @@ kct_status kct_plan_create(const kct_geometry *geom, int device, kct_plan **out)
         const int lu = std::atoi(e);
         if (lu == 16 || lu == 32 || lu == 64) p->fwd_lane_u = lu;
     }
+    // Tuning override: angles per forward workgroup (1 or 4).
+    if (const char *e = std::getenv("KCT_FWD_WAVE_ANGLES")) {
+        const int wa = std::atoi(e);
+        if (wa == 1 || wa == 4) p->fwd_wave_angles = wa;
+    }
+    // Tuning override: angles per block of the forward work order.
+    if (const char *e = std::getenv("KCT_FWD_ANGLE_BLOCK")) {
+        const int ab = std::atoi(e);
+        if (ab == 4 || ab == 8 || ab == 16 || ab == 32) p->fwd_angle_block = ab;
+    }
     DeviceGuard dg(device);
     if (!dg.ok) {
         delete p;

@@ -110,6 +110,8 @@ struct Plan {
     size_t split_bytes = 0;       // capacity of d_split
     bool fwd_prefetch = true;     // forward projector gathers one segment ahead
     int fwd_lane_u = 16;          // forward wave patch: lane_u x (64 / lane_u) rays (64, 32 or 16)
+    int fwd_wave_angles = 4;      // angles per forward workgroup: 1 (64 x 4 pixels) or 4 (one patch)
+    int fwd_angle_block = 8;      // forward work order: angles per block (4, 8, 16 or 32)
     bool bwd_acc_lds = true;      // back projector keeps per-voxel sums in LDS
     size_t bwd_lds = 0;
     int64_t n_vox() const { return int64_t(gp.nx) * gp.ny * gp.nz; }

@@ -6,9 +6,15 @@
 // rate on CDNA4, so the per-coefficient length carries ~1e-16 relative error
 // instead of the ~1e-5 an FP32 parametrisation of a 256-voxel ray would.
 //
-// Launch shape: a workgroup is 64 adjacent pixels of 4 adjacent detector rows
-// of one angle (one wave per row), so the lanes of a wave trace neighbouring
-// rays that cross the same voxel columns.  Lanes map to u, and neighbouring u
+// Launch shape: each wave traces a compact patch of neighbouring pixels of
+// one angle (16 x 4 by default), so its lanes follow rays that cross the same
+// voxel columns.  By default a workgroup's 4 waves trace the same patch at 4
+// consecutive angles (wave_angles = 4): rays of neighbouring angles through
+// one pixel nearly coincide, so those waves gather the same lines at nearly
+// the same time and the CU's L1 and the XCD's L2 serve them once.  (The
+// alternative, 4 waves tiling a 64 x 4 pixel block of one angle, is 20 %
+// slower on 256^3 / 360 x 512^2 and 60 % slower on a 1500^3 volume whose
+// gathers then miss L2 half of the time.)  Lanes map to u, and neighbouring u
 // are displaced along e_u, which is close to y for angles with |cos| >= |sin|:
 // for those angles the kernel reads a y-fastest copy of the volume so that a
 // wave's gather touches a few contiguous runs instead of 64 scattered lines.
@@ -85,18 +91,21 @@ __device__ inline double one_if(bool c)
     return __builtin_bit_cast(double, uint64_t(c ? 0x3ff00000u : 0u) << 32);
 }
 
-// Work order: angle blocks of FWD_AB angles; inside a block, detector row
-// bands of 4 rows; inside a band, the FWD_AB angles; inside an angle, the
-// 64-pixel u tiles.  The ~256 workgroups an XCD keeps in flight then cover a
-// few row bands of a handful of neighbouring angles, whose rays cross the
-// same few z-slices of the volume: that working set fits the XCD's 4 MB L2.
-constexpr int FWD_AB = 8;
+// Work order: blocks of angle_block angles (8 by default); inside a block,
+// detector row bands (4 rows, or one wave patch's rows with wave_angles = 4);
+// inside a band, the block's angles (in groups of 4 with wave_angles = 4) and
+// the u tiles.  With one angle per workgroup the angles are the slower index,
+// with 4 the u tiles are, so that the workgroups holding the block's angles
+// of one patch start together.  The ~256 workgroups an XCD keeps in flight
+// then cover a few row bands of a handful of neighbouring angles, whose rays
+// cross the same few z-slices of the volume.
 
-// One 64 x 4 ray tile (logical workgroup index `logical`).
+// One workgroup tile (logical workgroup index `logical`): 64 x 4 pixels of
+// one angle, or a lane_u x (64 / lane_u) patch at 4 angles.
 template <typename TV, typename TP, typename OFF, bool PREFETCH>
 __device__ inline void fwd_tile(const TV *__restrict__ vpad, TP *__restrict__ proj, const AngleGeo *__restrict__ tab,
                                 const GeoParams &g, const PadLayout &pl, int tiles_u, int tiles_v, int lane_u,
-                                int64_t logical,
+                                int wave_angles, int angle_block, int64_t logical,
                                 const Epilogue &ep, double *red)
 {
     double c0 = ep.c[0], c1 = ep.c[1];
@@ -105,23 +114,36 @@ __device__ inline void fwd_tile(const TV *__restrict__ vpad, TP *__restrict__ pr
         c1 = ep.scal[ep.coef_idx + 1];
     }
 
-    const int per_band = FWD_AB * tiles_u;
+    // Each wave traces a lane_u x (64 / lane_u) patch (16 x 4 by default).
+    // Rays of adjacent rows follow nearly the same voxels, so a compact patch
+    // sends fewer requests per gather to L2 than a 64-wide row does: on
+    // 256^3 / 360 x 512^2, 5.4 instead of 6.5 L2 requests per gather and 20.6
+    // instead of 22.7 ms per projection.
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int rows_w = 64 / lane_u;
+    const int n_at = angle_block / wave_angles; // angle groups per block
+    const int per_band = n_at * tiles_u;
     const int per_block = per_band * tiles_v;
     const int ab = int(logical / per_block);
     const int r1 = int(logical - int64_t(ab) * per_block);
     const int tvi = r1 / per_band;
     const int r2 = r1 - tvi * per_band;
-    const int ai = r2 / tiles_u, tui = r2 - ai * tiles_u;
-    const int a = ab * FWD_AB + ai;
-    // Each wave traces a lane_u x (64 / lane_u) patch of the 64 x 4 tile
-    // (16 x 4 by default).  Rays of adjacent rows follow nearly the same
-    // voxels, so a compact patch sends fewer requests per gather to L2 than a
-    // 64-wide row does: on 256^3 / 360 x 512^2, 5.4 instead of 6.5 L2
-    // requests per gather and 20.6 instead of 22.7 ms per projection.
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int waves_u = FWD_TU / lane_u, rows_w = 64 / lane_u;
-    const int iu = tui * FWD_TU + (wv % waves_u) * lane_u + lane % lane_u;
-    const int iv = tvi * FWD_TV + (wv / waves_u) * rows_w + lane / lane_u;
+    int a, iu, iv;
+    if (wave_angles == 1) { // tiles of 64 x 4 pixels; waves tile them
+        const int ai = r2 / tiles_u, tui = r2 - ai * tiles_u;
+        const int waves_u = FWD_TU / lane_u;
+        a = ab * angle_block + ai;
+        iu = tui * FWD_TU + (wv % waves_u) * lane_u + lane % lane_u;
+        iv = tvi * FWD_TV + (wv / waves_u) * rows_w + lane / lane_u;
+    } else { // tiles of one wave patch; wave w takes angle 4 * group + w
+        const int tui = r2 / n_at, ag = r2 - tui * n_at;
+        a = ab * angle_block + ag * 4 + wv;
+        iu = tui * lane_u + lane % lane_u;
+        iv = tvi * rows_w + lane / lane_u;
+    }
+    // The angle is uniform over the wave; saying so keeps its table row in
+    // scalar registers.
+    a = __builtin_amdgcn_readfirstlane(a);
     const bool valid = a < g.na && iu < g.nu && iv < g.nv;
 
     float acc = 0.f;
@@ -268,8 +290,8 @@ __device__ inline void fwd_tile(const TV *__restrict__ vpad, TP *__restrict__ pr
 template <typename TV, typename TP, typename OFF, bool PREFETCH>
 __global__ __launch_bounds__(256) void k_forward(const TV *__restrict__ vpad, TP *__restrict__ proj,
                                                  const AngleGeo *__restrict__ tab, GeoParams g, PadLayout pl,
-                                                 int tiles_u, int tiles_v, int lane_u, int64_t groups,
-                                                 int64_t launch,
+                                                 int tiles_u, int tiles_v, int lane_u, int wave_angles,
+                                                 int angle_block, int64_t groups, int64_t launch,
                                                  Epilogue ep)
 {
     __shared__ double red[4];
@@ -278,9 +300,22 @@ __global__ __launch_bounds__(256) void k_forward(const TV *__restrict__ vpad, TP
     for (int64_t b = blockIdx.x; b < launch; b += gridDim.x) {
         const int64_t logical = (b & 7) * g8 + (b >> 3);
         if (logical >= groups) continue;
-        fwd_tile<TV, TP, OFF, PREFETCH>(vpad, proj, tab, g, pl, tiles_u, tiles_v, lane_u, logical, ep, red);
+        fwd_tile<TV, TP, OFF, PREFETCH>(vpad, proj, tab, g, pl, tiles_u, tiles_v, lane_u, wave_angles, angle_block,
+                                         logical, ep, red);
         __syncthreads(); // red[] is reused by the next tile's reduction
     }
+}
+
+// Workgroup tiles along u and v, and the workgroup count: 64 x 4 pixel
+// tiles of single angles, or wave-patch tiles of 4 angles.
+int64_t fwd_tiling(const Plan &p, int &tiles_u, int &tiles_v)
+{
+    const int tu = p.fwd_wave_angles == 1 ? FWD_TU : p.fwd_lane_u;
+    const int tv = p.fwd_wave_angles == 1 ? FWD_TV : 64 / p.fwd_lane_u;
+    tiles_u = (p.gp.nu + tu - 1) / tu;
+    tiles_v = (p.gp.nv + tv - 1) / tv;
+    const int64_t blocks = (p.gp.na + p.fwd_angle_block - 1) / p.fwd_angle_block;
+    return blocks * (p.fwd_angle_block / p.fwd_wave_angles) * tiles_u * tiles_v;
 }
 
 template <typename TIN, typename TOUT>
@@ -296,16 +331,16 @@ kct_status pad_typed(Plan &p, const void *vol, void *pad, hipStream_t st)
 template <typename TV, typename TP>
 kct_status fwd_typed(Plan &p, const void *pad, void *proj, const Epilogue &ep, hipStream_t st)
 {
-    const int tiles_u = (p.gp.nu + FWD_TU - 1) / FWD_TU, tiles_v = (p.gp.nv + FWD_TV - 1) / FWD_TV;
-    const int64_t groups = fwd_num_groups(p);
+    int tiles_u = 0, tiles_v = 0;
+    const int64_t groups = fwd_tiling(p, tiles_u, tiles_v);
     const int64_t launch = ((groups + 7) / 8) * 8;
     const unsigned grid = unsigned(std::min<int64_t>(launch, FWD_MAX_BLOCKS));
     // 32-bit byte offsets when both padded copies fit in 4 GiB.
     const bool small = 2 * p.pad.vox * int64_t(sizeof(TV)) < int64_t(0xffffffffLL);
 #define KCT_FWD_LAUNCH(OFF_T, PF)                                                                                  \
     hipLaunchKernelGGL((k_forward<TV, TP, OFF_T, PF>), dim3(grid), dim3(256), 0, st, static_cast<const TV *>(pad), \
-                       static_cast<TP *>(proj), p.d_tab, p.gp, p.pad, tiles_u, tiles_v, p.fwd_lane_u, groups, launch, \
-                       ep)
+                       static_cast<TP *>(proj), p.d_tab, p.gp, p.pad, tiles_u, tiles_v, p.fwd_lane_u,                 \
+                       p.fwd_wave_angles, p.fwd_angle_block, groups, launch, ep)
     if (small) {
         if (p.fwd_prefetch) KCT_FWD_LAUNCH(uint32_t, true);
         else KCT_FWD_LAUNCH(uint32_t, false);
@@ -367,9 +402,8 @@ kct_status launch_pad_volume_as(Plan &p, const void *vol, int in_dtype, int out_
 
 int64_t fwd_num_groups(const Plan &p)
 {
-    const int tiles_u = (p.gp.nu + FWD_TU - 1) / FWD_TU, tiles_v = (p.gp.nv + FWD_TV - 1) / FWD_TV;
-    const int64_t blocks = (p.gp.na + FWD_AB - 1) / FWD_AB;
-    return blocks * FWD_AB * tiles_u * tiles_v;
+    int tiles_u = 0, tiles_v = 0;
+    return fwd_tiling(p, tiles_u, tiles_v);
 }
 
 // Project the padded copies in `pad` (built by launch_pad_volume with
