@@ -63,6 +63,8 @@ def timed(fn, reps, torch):
 
 def iter_rate(plan, b, solver, warmup, steps, torch, vec_dtype=None):
     """Iterations/s of `solver` over `steps` iterations after `warmup` ones."""
+    import numpy as np
+
     st = plan.state(b, solver, warmup + steps, vec_dtype=vec_dtype or torch.float32)
     st.step(warmup)
     torch.cuda.synchronize()
@@ -75,6 +77,12 @@ def iter_rate(plan, b, solver, warmup, steps, torch, vec_dtype=None):
     ms = e0.elapsed_time(e1)
     hist = st.history.cpu().numpy()
     st.close()
+    # A run that ended early (breakdown, a non-finite value, the stop rule)
+    # skips the rest of its kernels: its rate would not be an iteration rate.
+    done = np.flatnonzero(hist[:, 3])
+    if done.size:
+        raise RuntimeError(f"{solver} stopped at iteration {done[0] + 1} of {warmup + steps} (done code "
+                           f"{int(hist[done[0], 3])}); no iteration rate")
     return steps / (ms / 1000.0), ms, hist
 
 
@@ -355,6 +363,10 @@ def main():
                               tv_eps=sol["eps"])
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
+            done = np.flatnonzero(h.cpu().numpy()[:, 3])
+            if done.size:
+                raise RuntimeError(f"IRN-TV stopped at inner iteration {done[0] + 1} (done code "
+                                   f"{int(h[done[0], 3])}); no timing")
             rep["irn_tv_1x2_s"] = round(dt, 3)
             rep["irn_tv_full_extrapolated_s"] = round(dt / inner * sol["n_outer"] * sol["n_inner"], 1)
             rep["irn_tv_full"] = f"{sol['n_outer']} outer x {sol['n_inner']} inner, lambda {sol['lam']}"

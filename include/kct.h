@@ -97,6 +97,26 @@ typedef struct kct_plan kct_plan;
  * to the device.  Returns KCT_E_GEOMETRY for a geometry outside the
  * convention.  `*out` receives the plan, owned by the caller until
  * kct_plan_destroy.
+ *
+ * The plan also fixes the projectors' launch shapes from the geometry.  For
+ * tuning, these environment variables, read here, override the choice
+ * (values outside the listed sets are ignored):
+ *   KCT_FWD_PREFETCH     0 or 1   forward gathers one segment ahead (1)
+ *   KCT_FWD_LANES_U      16, 32, 64  pixels per wave row in the forward
+ *                                 (32 when neighbouring rays are a voxel or
+ *                                 more apart at the axis, else 16)
+ *   KCT_FWD_WAVE_ANGLES  1 or 4   angles per forward workgroup (4)
+ *   KCT_FWD_ANGLE_BLOCK  4, 8, 16, 32  angles per block of the forward's
+ *                                 work order (8)
+ *   KCT_FWD_PAD_F32      0 or 1   the forward widens a 16-bit volume into FP32
+ *                                 padded copies (1 while those fit in 4 GiB)
+ *   KCT_BWD_KZ           1, 8, 16 voxels per back-projector thread along z
+ *   KCT_BWD_ACC          0 or 1   back-projector sums in registers or LDS (1)
+ *   KCT_BWD_SPLIT        1..16    angle chunks of the back projection
+ *                                 (more than 1 only for small volumes)
+ * The forward settings give bitwise-equal projections; they regroup only
+ * the per-workgroup partial sums that the solvers reduce.  KCT_BWD_SPLIT
+ * changes the order of the FP32 sums.
  */
 kct_status kct_plan_create(const kct_geometry *geom, int device, kct_plan **out);
 

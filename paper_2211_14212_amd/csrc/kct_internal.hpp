@@ -112,6 +112,7 @@ struct Plan {
     int fwd_lane_u = 16;          // forward wave patch: lane_u x (64 / lane_u) rays (64, 32 or 16)
     int fwd_wave_angles = 4;      // angles per forward workgroup: 1 (64 x 4 pixels) or 4 (one patch)
     int fwd_angle_block = 8;      // forward work order: angles per block (4, 8, 16 or 32)
+    bool fwd_pad_f32 = true;      // forward: 16-bit volumes are padded into FP32 copies (small volumes)
     bool bwd_acc_lds = true;      // back projector keeps per-voxel sums in LDS
     size_t bwd_lds = 0;
     int64_t n_vox() const { return int64_t(gp.nx) * gp.ny * gp.nz; }
@@ -141,6 +142,10 @@ kct_status check_hip(hipError_t e, const char *what);
 // Launchers (one per kernel family).  Return KCT_OK or KCT_E_DEVICE.
 kct_status launch_pad_volume(Plan &p, const void *vol, int dtype, void *pad, hipStream_t st);
 kct_status launch_pad_volume_as(Plan &p, const void *vol, int in_dtype, int out_dtype, void *pad, hipStream_t st);
+// Storage of the forward's padded copies for a volume stored in `vol_dtype`:
+// FP32 when the plan widens 16-bit volumes (exact, and the FP32 gather is
+// faster), else the volume's own type.
+inline int fwd_pad_dtype(const Plan &p, int vol_dtype) { return p.fwd_pad_f32 ? int(KCT_F32) : vol_dtype; }
 int64_t fwd_num_groups(const Plan &p);
 kct_status launch_forward(Plan &p, const void *pad, int vol_dtype, void *proj, int proj_dtype,
                           const Epilogue &ep, hipStream_t st);

@@ -147,6 +147,24 @@ def test_forward_workgroup_shapes_agree_bitwise(kct, name, lanes, monkeypatch):
         assert torch.equal(outs[0], o)
 
 
+@pytest.mark.parametrize("dt", [torch.float16, torch.bfloat16])
+def test_forward_16bit_padding_widths_agree_bitwise(kct, dt, monkeypatch):
+    """A 16-bit volume's padded copies in FP32 (the default) or in its own
+    type (KCT_FWD_PAD_F32=0) hold the same values: the projections are
+    bitwise equal, in FP32 and in 16-bit output storage."""
+    gd = _geoms()["ragged"]
+    x = torch.from_numpy(synth.random_volume(tuple(gd[k] for k in ("nz", "ny", "nx")), 10)).to(DEV).to(dt)
+    outs = []
+    for wide in ("1", "0"):
+        monkeypatch.setenv("KCT_FWD_PAD_F32", wide)
+        plan = kct.Plan(kct.Geometry.from_dict(gd))
+        outs.append((plan.forward(x, out_dtype=torch.float32), plan.forward(x)))
+        torch.cuda.synchronize()
+        plan.close()
+    assert outs[0][1].dtype == dt
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+
+
 def test_backward_angle_split(kct, monkeypatch):
     """Small volumes split the back projector's angles over chunks of
     workgroups (32^3: 16 chunks) and sum the partial volumes in chunk order:
