@@ -218,6 +218,12 @@ kct_status kct_plan_create(const kct_geometry *geom, int device, kct_plan **out)
         s = check_hip(hipMemcpy(p->d_invv, invv.data(), sizeof(double) * geom->nv, hipMemcpyHostToDevice),
                       "plan table upload");
     if (s == KCT_OK) s = check_hip(hipMemset(p->d_err, 0, sizeof(int)), "plan flag reset");
+    if (s == KCT_OK)
+        s = check_hip(hipMalloc(&p->d_dlen, sizeof(float) * size_t(geom->nu) * size_t(geom->nv)),
+                      "plan table allocation");
+    if (s == KCT_OK) s = launch_ray_lengths(*p);
+    // The tables are used from any stream: finish them before returning.
+    if (s == KCT_OK) s = check_hip(hipDeviceSynchronize(), "plan table build");
     if (s != KCT_OK) {
         kct_plan_destroy(p);
         return s;
@@ -232,6 +238,7 @@ kct_status kct_plan_destroy(kct_plan *p)
     DeviceGuard dg(p->device);
     if (p->d_tab) (void)hipFree(p->d_tab);
     if (p->d_invv) (void)hipFree(p->d_invv);
+    if (p->d_dlen) (void)hipFree(p->d_dlen);
     if (p->d_err) (void)hipFree(p->d_err);
     if (p->d_pad) (void)hipFree(p->d_pad);
     if (p->d_split) (void)hipFree(p->d_split);
@@ -242,7 +249,8 @@ kct_status kct_plan_destroy(kct_plan *p)
 kct_status kct_plan_device_bytes(const kct_plan *p, size_t *bytes)
 {
     if (!p || !bytes) return fail(KCT_E_INVALID_ARG, "NULL argument");
-    *bytes = sizeof(AngleGeo) * p->gp.na + sizeof(double) * p->gp.nv + sizeof(int) + p->pad_bytes + p->split_bytes;
+    *bytes = sizeof(AngleGeo) * p->gp.na + sizeof(double) * p->gp.nv + sizeof(float) * size_t(p->gp.nv) * p->gp.nu +
+             sizeof(int) + p->pad_bytes + p->split_bytes;
     return KCT_OK;
 }
 

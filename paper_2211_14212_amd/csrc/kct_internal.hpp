@@ -100,6 +100,7 @@ struct Plan {
     PadLayout pad{};
     AngleGeo *d_tab = nullptr;   // per-angle table
     double *d_invv = nullptr;    // 1/v per detector row (0 where v == 0)
+    float *d_dlen = nullptr;     // |pixel centre - source| (mm) per detector pixel, [nv][nu]
     void *d_pad = nullptr;       // padded volume copies for plain kct_forward calls
     size_t pad_bytes = 0;        // capacity of d_pad
     int *d_err = nullptr;         // back projector footprint overflow flag (0 = fine)
@@ -156,6 +157,8 @@ int64_t bwd_split_floats(const Plan &p);
 kct_status launch_backward(Plan &p, const void *proj, int proj_dtype, void *vol, int vol_dtype,
                            const Epilogue &ep, hipStream_t st);
 kct_status choose_bwd_shape(Plan &p);
+// Fill p.d_dlen (nv * nu floats) on the null stream.
+kct_status launch_ray_lengths(Plan &p);
 
 size_t dtype_size(int dt);
 bool dtype_ok(int dt);

@@ -82,10 +82,24 @@ __device__ inline Footprint tile_footprint(const AngleGeo &A, const GeoParams &g
     return f;
 }
 
+// |pixel centre - source| per detector pixel (angle-independent), the
+// factor the back projector applies to every staged value.
+__global__ __launch_bounds__(256) void k_ray_lengths(float *__restrict__ out, GeoParams g)
+{
+    const int64_t n = int64_t(g.nu) * g.nv;
+    const float dsd = float(g.dsd);
+    for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < n; e += int64_t(gridDim.x) * 256) {
+        const int iv = int(e / g.nu), iu = int(e - int64_t(iv) * g.nu);
+        const float uu = float((iu - g.cu) * g.du), vv = float((iv - g.cv) * g.dv);
+        out[e] = sqrtf(dsd * dsd + uu * uu + vv * vv);
+    }
+}
+
 template <typename TP, typename TV, int KZ, int NCM, bool ACC_LDS>
 __global__ __launch_bounds__(256) void k_backward(const TP *__restrict__ proj, TV *__restrict__ vol,
                                                   const AngleGeo *__restrict__ tab,
-                                                  const double *__restrict__ invv, GeoParams g, int tiles_x,
+                                                  const double *__restrict__ invv,
+                                                  const float *__restrict__ dlen, GeoParams g, int tiles_x,
                                                   int tiles_y, int64_t groups, int pw_max, int ph_max,
                                                   int fp_angles, int *err_flag, Epilogue ep)
 {
@@ -169,12 +183,22 @@ __global__ __launch_bounds__(256) void k_backward(const TP *__restrict__ proj, T
 
         __syncthreads(); // the previous angle's reads of LDS are done
         const TP *ya = proj + int64_t(a) * g.nv * g.nu;
-        for (int e = threadIdx.x; e < pw * ph; e += 256) {
-            const int r = e / pw, c = e - r * pw;
-            const int iu = iu_lo + c, iv = iv_lo + r;
-            const float uu = float((iu - g.cu) * g.du), vv = float((iv - g.cv) * g.dv);
-            const float yv = to_f32(ya[int64_t(iv) * g.nu + iu]);
-            patch[e] = yv * sqrtf(dsd * dsd + uu * uu + vv * vv);
+        {
+            // Patch element e = r * pw + c, walked without a division per
+            // element: each step of 256 advances (r, c) by (q, rem).
+            const int q = 256 / pw, rem = 256 - q * pw;
+            int r = threadIdx.x / pw, c = threadIdx.x - (threadIdx.x / pw) * pw;
+#pragma unroll 4
+            for (int e = threadIdx.x; e < pw * ph; e += 256) {
+                const int64_t pix = int64_t(iv_lo + r) * g.nu + (iu_lo + c);
+                patch[e] = to_f32(ya[pix]) * dlen[pix];
+                c += rem;
+                r += q;
+                if (c >= pw) {
+                    c -= pw;
+                    ++r;
+                }
+            }
         }
         for (int c = threadIdx.x; c < pw; c += 256) {
             // 1/d per axis; 0 marks a ray parallel to that axis's planes.
@@ -409,11 +433,11 @@ kct_status bwd_launch3(Plan &p, const void *proj, void *vol, const Epilogue &ep,
         if (p.bwd_acc_lds && KZ > 1)
             hipLaunchKernelGGL((k_backward<TP, TV, KZ, NCM, true>), grid, dim3(256),
                                p.bwd_lds + size_t(KZ) * 256 * sizeof(float), st, static_cast<const TP *>(proj),
-                               static_cast<TV *>(vol), p.d_tab, p.d_invv, p.gp, int(s.tiles_x), int(s.tiles_y),
+                               static_cast<TV *>(vol), p.d_tab, p.d_invv, p.d_dlen, p.gp, int(s.tiles_x), int(s.tiles_y),
                                s.groups, p.bwd_pw, p.bwd_ph, p.bwd_fp_angles, p.d_err, raw);
         else
             hipLaunchKernelGGL((k_backward<TP, TV, KZ, NCM, false>), grid, dim3(256), p.bwd_lds, st,
-                               static_cast<const TP *>(proj), static_cast<TV *>(vol), p.d_tab, p.d_invv, p.gp,
+                               static_cast<const TP *>(proj), static_cast<TV *>(vol), p.d_tab, p.d_invv, p.d_dlen, p.gp,
                                int(s.tiles_x), int(s.tiles_y), s.groups, p.bwd_pw, p.bwd_ph, p.bwd_fp_angles,
                                p.d_err, raw);
         const kct_status e = check_hip(hipGetLastError(), "back projection launch");
@@ -426,12 +450,12 @@ kct_status bwd_launch3(Plan &p, const void *proj, void *vol, const Epilogue &ep,
     if (p.bwd_acc_lds && KZ > 1) {
         hipLaunchKernelGGL((k_backward<TP, TV, KZ, NCM, true>), dim3(unsigned(launch)), dim3(256),
                            p.bwd_lds + size_t(KZ) * 256 * sizeof(float), st, static_cast<const TP *>(proj),
-                           static_cast<TV *>(vol), p.d_tab, p.d_invv, p.gp, int(s.tiles_x), int(s.tiles_y), s.groups,
+                           static_cast<TV *>(vol), p.d_tab, p.d_invv, p.d_dlen, p.gp, int(s.tiles_x), int(s.tiles_y), s.groups,
                            p.bwd_pw, p.bwd_ph, p.bwd_fp_angles, p.d_err, ep);
         return check_hip(hipGetLastError(), "back projection launch");
     }
     hipLaunchKernelGGL((k_backward<TP, TV, KZ, NCM, false>), dim3(unsigned(launch)), dim3(256), p.bwd_lds, st,
-                       static_cast<const TP *>(proj), static_cast<TV *>(vol), p.d_tab, p.d_invv, p.gp,
+                       static_cast<const TP *>(proj), static_cast<TV *>(vol), p.d_tab, p.d_invv, p.d_dlen, p.gp,
                        int(s.tiles_x), int(s.tiles_y), s.groups, p.bwd_pw, p.bwd_ph, p.bwd_fp_angles, p.d_err, ep);
     return check_hip(hipGetLastError(), "back projection launch");
 }
@@ -552,6 +576,14 @@ kct_status choose_bwd_shape(Plan &p)
         if (p.bwd_kz == 1) return fail(KCT_E_GEOMETRY, "detector footprint of a voxel tile exceeds LDS");
         p.bwd_kz = p.bwd_kz == 16 ? 8 : 1;
     }
+}
+
+kct_status launch_ray_lengths(Plan &p)
+{
+    const int64_t n = int64_t(p.gp.nu) * p.gp.nv;
+    const unsigned groups = unsigned(std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096)));
+    hipLaunchKernelGGL(k_ray_lengths, dim3(groups), dim3(256), 0, 0, p.d_dlen, p.gp);
+    return check_hip(hipGetLastError(), "ray length table launch");
 }
 
 kct_status launch_backward(Plan &p, const void *proj, int proj_dtype, void *vol, int vol_dtype,
