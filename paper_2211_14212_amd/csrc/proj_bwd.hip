@@ -274,25 +274,33 @@ __global__ __launch_bounds__(256) void k_backward(const TP *__restrict__ proj, T
                 }
             }
             const float *pcol = patch + (c_lo - iu_lo);
-            const float rmin = dsd * fast_rcp(cwmin), rmax = dsd * fast_rcp(cwmax);
+            // Detector rows per mm of z at the column's nearest and farthest
+            // corner from the source (both magnifications are positive).
+            const float ra = dsd * fast_rcp(cwmin) * idv, rb = dsd * fast_rcp(cwmax) * idv;
+            const float rhi = fmaxf(ra, rb), rlo = fminf(ra, rb);
+            const float cvp = cv + margin, cvm = cv - margin;
             const int r_end = iv_lo + ph - 1;
             // The z run, compiled for the wave's column count NC <= NCM.  Row
             // bounds come from the z-planes of the thread's voxels: voxel k
-            // spans rows [row_lo(z_k), row_hi(z_{k+1})].
+            // spans rows [row_lo(z_k), row_hi(z_{k+1})], where a plane at
+            // height z projects between rows cv + z * rlo and cv + z * rhi
+            // (ordered by the sign of z).  FP32 is enough: the bounds only
+            // select candidate rows, with a margin far above their rounding.
             auto zrun = [&](auto nct) {
                 constexpr int NC = decltype(nct)::value;
-                float zb = float(g.Z0 + k0 * g.vz);
-                float vlo_b = fminf(zb * rmin, zb * rmax);
+                const float zb = float(g.Z0 + k0 * g.vz), vzf = float(g.vz);
+                float lo_b = fmaf(zb, zb >= 0.f ? rlo : rhi, cvm);
 #pragma unroll(ACC_LDS ? 1 : KZ)
                 for (int kk = 0; kk < KZ; ++kk) {
                     const int k = k0 + kk;
-                    const float zt = float(g.Z0 + (k + 1) * g.vz);
-                    const float vhi_t = fmaxf(zt * rmin, zt * rmax);
-                    const float vlo_t = fminf(zt * rmin, zt * rmax);
+                    const float zt = fmaf(float(kk + 1), vzf, zb);
+                    const bool up = zt >= 0.f;
+                    const float hi_t = fmaf(zt, up ? rhi : rlo, cvp);
+                    const float lo_t = fmaf(zt, up ? rlo : rhi, cvm);
                     if (k < g.nz && nc > 0) {
                         const double z0 = g.Z0 + k * g.vz, z1 = z0 + g.vz;
-                        const int r_lo = max(iv_lo, int(ceilf(vlo_b * idv + cv - margin)));
-                        const int r_hi = min(r_end, int(floorf(vhi_t * idv + cv + margin)));
+                        const int r_lo = max(iv_lo, int(ceilf(lo_b)));
+                        const int r_hi = min(r_end, int(floorf(hi_t)));
                         float s = ACC_LDS ? accs[kk * 256 + threadIdx.x] : acc[ACC_LDS ? 0 : kk];
                         for (int r = r_lo; r <= r_hi; ++r) {
                             // 1/v of the row (a huge positive value for v = 0, which
@@ -314,7 +322,7 @@ __global__ __launch_bounds__(256) void k_backward(const TP *__restrict__ proj, T
                         if constexpr (ACC_LDS) accs[kk * 256 + threadIdx.x] = s;
                         else acc[ACC_LDS ? 0 : kk] = s;
                     }
-                    vlo_b = vlo_t;
+                    lo_b = lo_t;
                 }
             };
             if (NCM >= 2 && ncw <= 2) zrun(std::integral_constant<int, (NCM >= 2 ? 2 : NCM)>{});
