@@ -103,6 +103,8 @@ def load(path: str = LIB_PATH):
         "kct_version": ([], ctypes.c_char_p),
         "kct_debug_take_error_flag": ([vp], ctypes.c_int),
         "kct_debug_bwd_shape": ([vp, P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_int)], None),
+        "kct_debug_fwd_shape_geom": ([P(KctGeometry), P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_int),
+                                      P(ctypes.c_int)], ctypes.c_int),
         "kct_debug_bwd_shape_geom": ([P(KctGeometry), P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_int),
                                       P(ctypes.c_int)], ctypes.c_int),
     }

@@ -115,6 +115,44 @@ static void build_tables(Plan &p)
     p.pad.vox = p.pad.px * p.pad.py * p.pad.pz;
 }
 
+// The forward projector's launch shape for the plan's geometry, then the
+// tuning overrides from the environment.
+void choose_fwd_shape(Plan &p)
+{
+    const kct_geometry &g = p.geom;
+    // Forward wave patch: when neighbouring rays are at least a voxel apart
+    // at the rotation axis, a wider, flatter patch (32 x 2 pixels) touches
+    // fewer lines per gather than 16 x 4 (1500^3 at 10 um, 0.1 mm pixels at
+    // magnification 5.3: 3.65 against 3.93 s); with finer ray spacing 16 x 4
+    // is faster (256^3 at 0.5 mm, 0.4 mm pixels at 1.5: 17.3 against 17.8 ms).
+    if (g.du * g.dso / g.dsd >= std::min(g.vx, g.vy)) p.fwd_lane_u = 32;
+    // 16-bit volumes: FP32 padded copies gather faster while they are small
+    // (512^3: 240 against 290 ms per projection); once the FP32 copies pass
+    // 4 GiB, the 16-bit copies' halved gather traffic wins (1500^3: 3.64
+    // against 3.92 s).
+    p.fwd_pad_f32 = 2 * p.pad.vox * int64_t(sizeof(float)) < int64_t(0xffffffffLL);
+    // Tuning override: KCT_FWD_PREFETCH=0 selects the forward loop without
+    // the one-step-ahead gather.
+    if (const char *e = std::getenv("KCT_FWD_PREFETCH")) p.fwd_prefetch = std::atoi(e) != 0;
+    // Tuning override: the forward wave's patch width in detector columns.
+    if (const char *e = std::getenv("KCT_FWD_LANES_U")) {
+        const int lu = std::atoi(e);
+        if (lu == 16 || lu == 32 || lu == 64) p.fwd_lane_u = lu;
+    }
+    // Tuning override: KCT_FWD_PAD_F32=0 keeps 16-bit padded copies.
+    if (const char *e = std::getenv("KCT_FWD_PAD_F32")) p.fwd_pad_f32 = std::atoi(e) != 0;
+    // Tuning override: angles per forward workgroup (1 or 4).
+    if (const char *e = std::getenv("KCT_FWD_WAVE_ANGLES")) {
+        const int wa = std::atoi(e);
+        if (wa == 1 || wa == 4) p.fwd_wave_angles = wa;
+    }
+    // Tuning override: angles per block of the forward work order.
+    if (const char *e = std::getenv("KCT_FWD_ANGLE_BLOCK")) {
+        const int ab = std::atoi(e);
+        if (ab == 4 || ab == 8 || ab == 16 || ab == 32) p.fwd_angle_block = ab;
+    }
+}
+
 } // namespace kct
 
 using namespace kct;
@@ -163,37 +201,7 @@ kct_status kct_plan_create(const kct_geometry *geom, int device, kct_plan **out)
         delete p;
         return s;
     }
-    // Forward wave patch: when neighbouring rays are at least a voxel apart
-    // at the rotation axis, a wider, flatter patch (32 x 2 pixels) touches
-    // fewer lines per gather than 16 x 4 (1500^3 at 10 um, 0.1 mm pixels at
-    // magnification 5.3: 3.65 against 3.93 s); with finer ray spacing 16 x 4
-    // is faster (256^3 at 0.5 mm, 0.4 mm pixels at 1.5: 17.3 against 17.8 ms).
-    if (geom->du * geom->dso / geom->dsd >= std::min(geom->vx, geom->vy)) p->fwd_lane_u = 32;
-    // 16-bit volumes: FP32 padded copies gather faster while they are small
-    // (512^3: 240 against 290 ms per projection); once the FP32 copies pass
-    // 4 GiB, the 16-bit copies' halved gather traffic wins (1500^3: 3.64
-    // against 3.92 s).
-    p->fwd_pad_f32 = 2 * p->pad.vox * int64_t(sizeof(float)) < int64_t(0xffffffffLL);
-    // Tuning override: KCT_FWD_PREFETCH=0 selects the forward loop without
-    // the one-step-ahead gather.
-    if (const char *e = std::getenv("KCT_FWD_PREFETCH")) p->fwd_prefetch = std::atoi(e) != 0;
-    // Tuning override: the forward wave's patch width in detector columns.
-    if (const char *e = std::getenv("KCT_FWD_LANES_U")) {
-        const int lu = std::atoi(e);
-        if (lu == 16 || lu == 32 || lu == 64) p->fwd_lane_u = lu;
-    }
-    // Tuning override: KCT_FWD_PAD_F32=0 keeps 16-bit padded copies.
-    if (const char *e = std::getenv("KCT_FWD_PAD_F32")) p->fwd_pad_f32 = std::atoi(e) != 0;
-    // Tuning override: angles per forward workgroup (1 or 4).
-    if (const char *e = std::getenv("KCT_FWD_WAVE_ANGLES")) {
-        const int wa = std::atoi(e);
-        if (wa == 1 || wa == 4) p->fwd_wave_angles = wa;
-    }
-    // Tuning override: angles per block of the forward work order.
-    if (const char *e = std::getenv("KCT_FWD_ANGLE_BLOCK")) {
-        const int ab = std::atoi(e);
-        if (ab == 4 || ab == 8 || ab == 16 || ab == 32) p->fwd_angle_block = ab;
-    }
+    choose_fwd_shape(*p);
     DeviceGuard dg(device);
     if (!dg.ok) {
         delete p;
@@ -342,6 +350,25 @@ int kct_debug_bwd_shape_geom(const kct_geometry *geom, int *kz, int *ncmax, int 
     if (ncmax) *ncmax = p.bwd_ncmax;
     if (pw) *pw = p.bwd_pw;
     if (ph) *ph = p.bwd_ph;
+    return KCT_OK;
+}
+
+// Test hook: the forward launch shape a plan for `geom` would use, computed
+// on the host without touching a device.  Returns a kct_status.
+int kct_debug_fwd_shape_geom(const kct_geometry *geom, int *lane_u, int *wave_angles, int *angle_block, int *pad_f32)
+{
+    kct_status s = validate(geom);
+    if (s != KCT_OK) return s;
+    Plan p;
+    p.geom = *geom;
+    p.angles.assign(geom->angles, geom->angles + geom->n_angles);
+    p.geom.angles = p.angles.data();
+    build_tables(p);
+    choose_fwd_shape(p);
+    if (lane_u) *lane_u = p.fwd_lane_u;
+    if (wave_angles) *wave_angles = p.fwd_wave_angles;
+    if (angle_block) *angle_block = p.fwd_angle_block;
+    if (pad_f32) *pad_f32 = p.fwd_pad_f32 ? 1 : 0;
     return KCT_OK;
 }
 
