@@ -123,8 +123,10 @@ kct_status kct_plan_create(const kct_geometry *geom, int device, kct_plan **out)
 /* Free a plan and every device buffer it owns.  NULL is accepted. */
 kct_status kct_plan_destroy(kct_plan *plan);
 
-/* Device bytes the plan holds now (tables, padded volume copies and partial
- * volumes of plain kct_forward / kct_backproject calls). */
+/* Device bytes the plan holds now: its tables (per-angle geometry, 1/v per
+ * detector row, the ray length of every detector pixel: nu * nv floats) and
+ * the padded volume copies and partial volumes of plain kct_forward /
+ * kct_backproject calls. */
 kct_status kct_plan_device_bytes(const kct_plan *plan, size_t *bytes);
 
 /*
