@@ -62,10 +62,12 @@ def timed(fn, reps, torch):
 
 
 def iter_rate(plan, b, solver, warmup, steps, torch, vec_dtype=None):
-    """Iterations/s of `solver` over `steps` iterations after `warmup` ones."""
+    """Iterations/s of `solver` over `steps` iterations after `warmup` ones,
+    on a stream of its own (which lets CGLS replay a captured iteration)."""
     import numpy as np
 
-    st = plan.state(b, solver, warmup + steps, vec_dtype=vec_dtype or torch.float32)
+    st = plan.state(b, solver, warmup + steps, vec_dtype=vec_dtype or torch.float32,
+                    stream=torch.cuda.Stream(device=b.device))
     st.step(warmup)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

@@ -312,6 +312,11 @@ kct_status kct_state_create(kct_plan *plan, const kct_solve_params *params, cons
 /* Enqueue up to `n_steps` more iterations (the first call also enqueues the
  * initialisation).  Returns at once; the host counts iterations enqueued, so
  * no device synchronisation is needed. */
+/* (KCT_SOLVE_GRAPHS=1 in the environment at kct_state_create: a CGLS run
+ * without flags captures its second iteration into a HIP graph and replays
+ * it for the later steps.  That needs a stream that can be captured, not the
+ * legacy default stream; otherwise, and on any capture failure, the kernels
+ * are enqueued as usual.  The results are bitwise the same either way.) */
 kct_status kct_state_step(kct_state *state, int32_t n_steps);
 
 /* Iterations enqueued so far and whether all requested iterations are. */

@@ -265,11 +265,14 @@ class State:
         self.n_iter = n_iter
         self._args = dict(solver=solver, n_iter=n_iter, lam=lam, vec_dtype=vec_dtype, options=dict(tv))
         self.stream = stream if stream is not None else torch.cuda.current_stream(plan.device)
-        self.x = torch.empty(plan.geom.vol_shape, dtype=torch.float32, device=plan.device)
         need = plan.workspace_bytes(solver, n_iter, lam, vec_dtype, **tv)
-        self.workspace = torch.empty(need, dtype=torch.uint8, device=plan.device)
         rows = plan.history_rows(solver, n_iter, tv.get("tv_outer", 0), tv.get("tv_inner", 0))
-        self.history = torch.zeros((max(rows, 1), KCT_HIST_COLS), dtype=torch.float64, device=plan.device)
+        # Allocated (and the history zeroed) on the run's stream, ordered
+        # before its kernels.
+        with torch.cuda.stream(self.stream):
+            self.x = torch.empty(plan.geom.vol_shape, dtype=torch.float32, device=plan.device)
+            self.workspace = torch.empty(need, dtype=torch.uint8, device=plan.device)
+            self.history = torch.zeros((max(rows, 1), KCT_HIST_COLS), dtype=torch.float64, device=plan.device)
         p = _params(solver, n_iter, lam, vec_dtype, **tv)
         h = ctypes.c_void_p()
         args = (plan.handle, ctypes.byref(p), ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(self.x.data_ptr()),

@@ -256,3 +256,44 @@ def test_warm_start_rejected_where_it_does_not_apply(kct):
             plan.solve(bt, solver, 3, lam, x=x, warm_start=True, **kw)
     with pytest.raises(ValueError):
         plan.solve(bt, "cgls", 3, warm_start=True)
+
+
+@pytest.mark.parametrize("name,lam,vdt", [("cgls32", 0.0, torch.float32), ("medical48", 2.0, torch.float32),
+                                          ("cgls32", 0.0, torch.bfloat16)])
+def test_cgls_graph_replay_bitwise(kct, name, lam, vdt, monkeypatch):
+    """With KCT_SOLVE_GRAPHS=1, on a stream that can be captured, CGLS replays
+    one captured HIP graph per step from the second iteration on.  Steps are taken one at a time,
+    with eager work on the same stream and device synchronisations between
+    them. Every step's x and history rows must be bitwise those of the run
+    that enqueues every kernel (KCT_SOLVE_GRAPHS=0). On the legacy default
+    stream the state falls back to enqueueing the kernels."""
+    og, kg, b = _problem(name)
+    plan = kct.Plan(kg)
+    bt = torch.from_numpy(b).to(DEV)
+    torch.cuda.synchronize()
+    n = 7
+
+    def run(graphs, stream):
+        monkeypatch.setenv("KCT_SOLVE_GRAPHS", graphs)
+        st = plan.state(bt, "cgls", n, lam, vec_dtype=vdt, stream=stream)
+        xs = []
+        for k in range(n):
+            st.step(1)
+            with torch.cuda.stream(st.stream):
+                junk = torch.full((4096,), float(k), device=DEV)
+                junk.mul_(2.0).add_(1.0)  # eager work between the replays
+            torch.cuda.synchronize()
+            xs.append(st.x.clone())
+        h = st.history.clone()
+        st.close()
+        return xs, h
+
+    side = torch.cuda.Stream(device=DEV)
+    ref_x, ref_h = run("0", side)
+    got_x, got_h = run("1", side)
+    print(f"[graph {name} lam={lam} {vdt}] final |x| {float(got_x[-1].norm()):.6e}", flush=True)
+    for k in range(n):
+        assert torch.equal(got_x[k], ref_x[k]), f"step {k}"
+    assert torch.equal(got_h, ref_h)
+    dflt_x, dflt_h = run("1", torch.cuda.default_stream(DEV))
+    assert torch.equal(dflt_x[-1], ref_x[-1]) and torch.equal(dflt_h, ref_h)
