@@ -88,6 +88,30 @@ def iter_rate(plan, b, solver, warmup, steps, torch, vec_dtype=None):
     return steps / (ms / 1000.0), ms, hist
 
 
+def cpu_baseline_full_cgls(gd, b, n_iter):
+    """The whole FP64 oracle CGLS run of a small workload, on all host
+    threads and on one: iterations per second."""
+    import numpy as np
+
+    import oracle
+    from oracle import solvers
+
+    g = oracle.Geometry.from_dict(gd)
+    b64 = np.asarray(b, dtype=np.float64)
+    A, AT = (lambda v: oracle.forward(g, v)), (lambda y: oracle.adjoint(g, y))
+    cores = oracle.num_threads()
+    rates = {}
+    for nth in (cores, 1):
+        oracle.set_num_threads(nth)
+        t0 = time.perf_counter()
+        solvers.cgls(A, AT, b64, n_iter)
+        rates[nth] = n_iter / (time.perf_counter() - t0)
+    oracle.set_num_threads(cores)
+    return {"value": rates[cores], "unit": "CGLS it/s", "cores": cores, "kind": "oracle",
+            "sample": f"the full FP64 CGLS-{n_iter} of the workload (from the same noisy b)",
+            "single_thread_it_per_s": rates[1]}
+
+
 def cpu_baseline(gd, x, n_angles_sample=24):
     """The FP64 oracle on the host: forward and scatter adjoint over a subset
     of the angles, scaled to one CGLS iteration of the full workload."""
@@ -463,6 +487,10 @@ def main():
         log("[bench] cpu baseline (oracle)")
         cpu = cpu_baseline(gd, x_true)
         log(f"[bench] cpu {cpu['value']:.4f} it/s on {cpu['cores']} threads")
+    elif not args.no_cpu_baseline and wl == "cgls32":
+        log("[bench] cpu baseline (oracle, full CGLS-20)")
+        cpu = cpu_baseline_full_cgls(gd, b.cpu().numpy(), 20)
+        log(f"[bench] cpu {cpu['value']:.1f} it/s on {cpu['cores']} threads, {cpu['single_thread_it_per_s']:.1f} on 1")
 
     out = {
         "metric": METRIC, "value": round(cgls_rate, 3), "unit": "CGLS it/s", "n_gpus": 1, "steps": args.steps,

@@ -26,8 +26,9 @@ the adjoint identity, the Krylov-subspace optimality that defines each solver
 independent LSQR/LSMR, dense normal-equation solves, and hand-derived values
 in ``tests/golden/``.  No function here is "parity unpinned".
 """
-from .projector import Geometry, adjoint, build, count_nnz, forward, forward_rays, num_threads, ray_segments
+from .projector import (Geometry, adjoint, build, count_nnz, forward, forward_rays, num_threads, ray_segments,
+                        set_num_threads)
 from . import dense, interp, solvers
 
-__all__ = ["Geometry", "forward", "adjoint", "forward_rays", "ray_segments", "count_nnz", "num_threads", "build",
-           "dense", "interp", "solvers"]
+__all__ = ["Geometry", "forward", "adjoint", "forward_rays", "ray_segments", "count_nnz", "num_threads",
+           "set_num_threads", "build", "dense", "interp", "solvers"]

@@ -111,6 +111,7 @@ def _load():
                                              ctypes.c_int64, P(ctypes.c_double)]
             lib.ora_count_nnz.argtypes = [P(_CGeom), P(ctypes.c_int64), P(ctypes.c_int64)]
             lib.ora_num_threads.restype = ctypes.c_int
+            lib.ora_set_num_threads.argtypes = [ctypes.c_int]
             _lib = lib
     return _lib
 
@@ -189,3 +190,8 @@ def count_nnz(g: Geometry):
 
 def num_threads() -> int:
     return int(_load().ora_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads for later projector calls (timing only; results do not depend on it)."""
+    _load().ora_set_num_threads(int(n))

@@ -324,3 +324,13 @@ int ora_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads used by later calls (timing only; results do not depend on it). */
+void ora_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
