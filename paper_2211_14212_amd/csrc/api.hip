@@ -229,9 +229,14 @@ kct_status kct_plan_create(const kct_geometry *geom, int device, kct_plan **out)
     if (s == KCT_OK)
         s = check_hip(hipMalloc(&p->d_dlen, sizeof(float) * size_t(geom->nu) * size_t(geom->nv)),
                       "plan table allocation");
-    if (s == KCT_OK) s = launch_ray_lengths(*p);
-    // The tables are used from any stream: finish them before returning.
-    if (s == KCT_OK) s = check_hip(hipDeviceSynchronize(), "plan table build");
+    // The tables are used from any stream: build them on a private stream and
+    // wait for that stream only (work the caller has in flight on other
+    // streams, such as other requests' iterations, is not waited for).
+    hipStream_t ts = nullptr;
+    if (s == KCT_OK) s = check_hip(hipStreamCreateWithFlags(&ts, hipStreamNonBlocking), "plan stream creation");
+    if (s == KCT_OK) s = launch_ray_lengths(*p, ts);
+    if (s == KCT_OK) s = check_hip(hipStreamSynchronize(ts), "plan table build");
+    if (ts) (void)hipStreamDestroy(ts);
     if (s != KCT_OK) {
         kct_plan_destroy(p);
         return s;

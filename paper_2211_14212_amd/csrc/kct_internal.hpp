@@ -157,8 +157,8 @@ int64_t bwd_split_floats(const Plan &p);
 kct_status launch_backward(Plan &p, const void *proj, int proj_dtype, void *vol, int vol_dtype,
                            const Epilogue &ep, hipStream_t st);
 kct_status choose_bwd_shape(Plan &p);
-// Fill p.d_dlen (nv * nu floats) on the null stream.
-kct_status launch_ray_lengths(Plan &p);
+// Fill p.d_dlen (nv * nu floats) on stream `st`.
+kct_status launch_ray_lengths(Plan &p, hipStream_t st);
 
 size_t dtype_size(int dt);
 bool dtype_ok(int dt);

@@ -586,11 +586,11 @@ kct_status choose_bwd_shape(Plan &p)
     }
 }
 
-kct_status launch_ray_lengths(Plan &p)
+kct_status launch_ray_lengths(Plan &p, hipStream_t st)
 {
     const int64_t n = int64_t(p.gp.nu) * p.gp.nv;
     const unsigned groups = unsigned(std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096)));
-    hipLaunchKernelGGL(k_ray_lengths, dim3(groups), dim3(256), 0, 0, p.d_dlen, p.gp);
+    hipLaunchKernelGGL(k_ray_lengths, dim3(groups), dim3(256), 0, st, p.d_dlen, p.gp);
     return check_hip(hipGetLastError(), "ray length table launch");
 }
 
