@@ -193,5 +193,10 @@ def num_threads() -> int:
 
 
 def set_num_threads(n: int) -> None:
-    """Threads for later projector calls (timing only; results do not depend on it)."""
+    """Threads for later projector calls.
+
+    ``forward`` gives the same result for any count (each ray is summed by one
+    thread).  ``adjoint`` sums one partial volume per thread, in thread order,
+    so its result can change with the count at FP64 rounding level (about
+    1e-16 relative)."""
     _load().ora_set_num_threads(int(n))

@@ -325,7 +325,9 @@ int ora_num_threads(void)
 #endif
 }
 
-/* Threads used by later calls (timing only; results do not depend on it). */
+/* Threads used by later calls.  The forward does not depend on the count; the
+ * adjoint's per-thread partial volumes, summed in thread order, make its result
+ * change with the count at FP64 rounding level. */
 void ora_set_num_threads(int n)
 {
 #ifdef _OPENMP
