@@ -25,9 +25,12 @@
  *
  * Ownership.  The caller allocates and owns every device buffer passed in
  * (volumes, projections, right-hand side, solution, workspace, history).  A
- * plan owns its geometry tables and the padded volume copies the forward
- * projector reads; kct_plan_device_bytes reports that memory.  The library
- * never frees caller memory.
+ * plan owns its geometry tables, the back projector's partial volumes for
+ * small volumes (allocated with the plan) and, after kct_plan_reserve, the
+ * padded volume copies that plain kct_forward calls read;
+ * kct_plan_device_bytes reports that memory.  The library never frees caller
+ * memory.  Only kct_plan_create, kct_plan_reserve and kct_plan_destroy
+ * allocate or free device memory; no other call does.
  *
  * Streams.  Every call that takes a `stream` (a hipStream_t, or NULL for the
  * null stream) only enqueues work on it and returns; the caller synchronises.
@@ -42,7 +45,12 @@
  * thread.  No C++ exception crosses this interface and the library never
  * aborts.  A launch failure returns KCT_E_DEVICE.  Krylov breakdown (a zero
  * norm, e.g. b = 0) is not an error: the remaining iterations leave x
- * unchanged and report it in the history.
+ * unchanged and report it in the history.  The back projector sizes its
+ * per-tile detector patch and per-voxel column count from bounds the plan
+ * derives from the geometry's extreme magnification; a footprint beyond them
+ * is not expected for any geometry the plan accepts, but if one occurs the
+ * sums are truncated and the library says so: kct_plan_check returns
+ * KCT_E_GEOMETRY, and a solve records done code 4 in its history.
  */
 #ifndef KCT_H
 #define KCT_H
@@ -114,6 +122,10 @@ typedef struct kct_plan kct_plan;
  *   KCT_BWD_ACC          0 or 1   back-projector sums in registers or LDS (1)
  *   KCT_BWD_SPLIT        1..16    angle chunks of the back projection
  *                                 (more than 1 only for small volumes)
+ *   KCT_BWD_TEST_PW_MAX  >= 1     test hook: caps the back projector's per-tile
+ *                                 patch width, so that the footprint overflow
+ *                                 report (kct_plan_check, history code 4) can
+ *                                 be exercised; the sums are then truncated
  * The forward settings give bitwise-equal projections; they regroup only
  * the per-workgroup partial sums that the solvers reduce.  KCT_BWD_SPLIT
  * changes the order of the FP32 sums.
@@ -123,17 +135,38 @@ kct_status kct_plan_create(const kct_geometry *geom, int device, kct_plan **out)
 /* Free a plan and every device buffer it owns.  NULL is accepted. */
 kct_status kct_plan_destroy(kct_plan *plan);
 
+/*
+ * Allocate the padded volume copies that plain kct_forward calls on volumes
+ * stored in `vol_dtype` read: 2 (nx+2)(ny+2)(nz+2) elements (FP32 for
+ * volumes the plan widens, else `vol_dtype`).  Nothing happens when the plan
+ * already holds enough.  Synchronous: replacing smaller copies first waits for
+ * the device.  Solves do not need this (they keep the copies in their
+ * workspace).  KCT_E_OOM if the allocation fails.
+ */
+kct_status kct_plan_reserve(kct_plan *plan, int32_t vol_dtype);
+
+/*
+ * Synchronous check of the projector calls made on `plan` so far: waits for
+ * `stream`, then reads and clears the plan's error flag.  KCT_OK, or
+ * KCT_E_GEOMETRY when a back projection since the last check met a voxel
+ * footprint wider than the plan's bounds (see Errors above) and returned
+ * truncated sums.  Work on other streams must be finished by the caller.
+ */
+kct_status kct_plan_check(kct_plan *plan, void *stream);
+
 /* Device bytes the plan holds now: its tables (per-angle geometry, 1/v per
- * detector row, the ray length of every detector pixel: nu * nv floats) and
- * the padded volume copies and partial volumes of plain kct_forward /
- * kct_backproject calls. */
+ * detector row, the ray length of every detector pixel: nu * nv floats), the
+ * back projector's partial volumes (small volumes) and the padded volume
+ * copies of kct_plan_reserve. */
 kct_status kct_plan_device_bytes(const kct_plan *plan, size_t *bytes);
 
 /*
  * Forward projection (paper Sec. 2: every Krylov iteration applies A once):
  * d_proj = A d_vol.  d_vol: [nz][ny][nx] of `vol_dtype`; d_proj:
  * [n_angles][nv][nu] of `proj_dtype`, overwritten.  Ray sums accumulate in
- * FP32; ray geometry is evaluated in FP64.  Enqueued on `stream`.
+ * FP32; ray geometry is evaluated in FP64.  Enqueued on `stream`.  The plan
+ * must hold padded copies for `vol_dtype` (kct_plan_reserve); otherwise
+ * KCT_E_BUDGET and nothing is enqueued.
  */
 kct_status kct_forward(kct_plan *plan, const void *d_vol, int32_t vol_dtype, void *d_proj,
                        int32_t proj_dtype, void *stream);
@@ -144,7 +177,8 @@ kct_status kct_forward(kct_plan *plan, const void *d_vol, int32_t vol_dtype, voi
  * d_vol = A^T d_proj.  Voxel-driven gather; FP32 accumulation.  Layouts as in
  * kct_forward; d_vol is overwritten.  For a small volume (too few voxel tiles
  * to fill the GPU) the angles are split over up to 16 chunks whose partial
- * volumes are summed in chunk order.  Enqueued on `stream`.
+ * volumes (allocated with the plan) are summed in chunk order.  Enqueued on
+ * `stream`.
  */
 kct_status kct_backproject(kct_plan *plan, const void *d_proj, int32_t proj_dtype, void *d_vol,
                            int32_t vol_dtype, void *stream);
@@ -234,7 +268,9 @@ typedef enum kct_lambda_rule {
  *       normalised and M[k+1, k]);
  *   [3] 1 if the method had broken down (zero norm) by this iteration, 2 if a
  *       scalar became non-finite, 3 if the explicit residual rule stopped it,
- *       else 0;
+ *       4 if a back projection of the run met a footprint wider than the
+ *       plan's bounds (its sums were truncated: x is not valid; see Errors at
+ *       the top of this file), else 0;
  *   [4] lambda_k, the Tikhonov parameter of iteration k (the fixed lambda, or
  *       hybrid LSQR's GCV / DP choice; IRN-TV: the TV weight lambda). */
 #define KCT_HIST_COLS 5
@@ -355,6 +391,26 @@ const char *kct_last_error(void);
 
 /* Library version string. */
 const char *kct_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Test hooks: launch shapes the plan logic chooses, read on the host        */
+/* ------------------------------------------------------------------------ */
+
+/* The back projector's shape for `geom` without touching a device: voxels per
+ * thread along z, the unrolled column count, and the per-tile detector patch
+ * bounds (columns, rows).  Any output may be NULL.  Returns a kct_status
+ * (geometry validation as kct_plan_create). */
+int kct_debug_bwd_shape_geom(const kct_geometry *geom, int *kz, int *ncmax, int *pw, int *ph);
+
+/* The forward's shape for `geom` without touching a device: pixels per wave
+ * row, angles per workgroup, angles per work-order block, and whether 16-bit
+ * volumes are widened into FP32 padded copies (1) or not (0).  Returns a
+ * kct_status. */
+int kct_debug_fwd_shape_geom(const kct_geometry *geom, int *lane_u, int *wave_angles, int *angle_block,
+                             int *pad_f32);
+
+/* The back projector's shape of an existing plan (as kct_debug_bwd_shape_geom). */
+void kct_debug_bwd_shape(const kct_plan *plan, int *kz, int *ncmax, int *pw, int *ph);
 
 #ifdef __cplusplus
 }

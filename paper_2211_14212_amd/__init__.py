@@ -129,6 +129,7 @@ class Plan:
         with torch.cuda.device(self.device):
             _lib.check(_lib.load().kct_plan_create(ctypes.byref(cg), device, ctypes.byref(h)), "kct_plan_create")
         self._h = h
+        self._reserved = set()  # volume storage types kct_plan_reserve was called for
 
     # -- lifetime ---------------------------------------------------------
     def close(self):
@@ -145,6 +146,18 @@ class Plan:
     @property
     def handle(self):
         return self._h
+
+    def reserve(self, vol_dtype=torch.float32):
+        """Allocate the padded volume copies that ``forward`` reads for volumes
+        stored in ``vol_dtype`` (kct_plan_reserve; synchronous, once)."""
+        with torch.cuda.device(self.device):
+            _lib.check(_lib.load().kct_plan_reserve(self._h, dtype_code(vol_dtype)), "kct_plan_reserve")
+
+    def check(self, stream=None):
+        """Wait for ``stream`` and raise KctError if a back projection since the
+        last check met a footprint beyond the plan's bounds (kct_plan_check)."""
+        with torch.cuda.device(self.device):
+            _lib.check(_lib.load().kct_plan_check(self._h, _stream_ptr(stream)), "kct_plan_check")
 
     def device_bytes(self) -> int:
         n = ctypes.c_size_t()
@@ -164,6 +177,9 @@ class Plan:
         if out is None:
             out = torch.empty(self.geom.proj_shape, dtype=out_dtype or vol.dtype, device=self.device)
         self._check(out, self.geom.proj_shape, "projections")
+        if vol.dtype not in self._reserved:
+            self.reserve(vol.dtype)
+            self._reserved.add(vol.dtype)
         with torch.cuda.device(self.device):
             _lib.check(_lib.load().kct_forward(self._h, ctypes.c_void_p(vol.data_ptr()), dtype_code(vol.dtype),
                                                ctypes.c_void_p(out.data_ptr()), dtype_code(out.dtype),

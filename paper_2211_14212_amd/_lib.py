@@ -32,7 +32,8 @@ KCT_HIST_COLS = 5
 KCT_LAMBDA_FIXED, KCT_LAMBDA_GCV, KCT_LAMBDA_DP = 0, 1, 2
 
 EXPORTED = [
-    "kct_plan_create", "kct_plan_destroy", "kct_plan_device_bytes", "kct_forward", "kct_backproject",
+    "kct_plan_create", "kct_plan_destroy", "kct_plan_reserve", "kct_plan_check", "kct_plan_device_bytes",
+    "kct_forward", "kct_backproject",
     "kct_backproject_interp",
     "kct_solve_workspace_bytes", "kct_solve", "kct_state_create", "kct_state_step", "kct_state_progress",
     "kct_state_resume",
@@ -87,6 +88,8 @@ def load(path: str = LIB_PATH):
     sig = {
         "kct_plan_create": ([P(KctGeometry), ctypes.c_int, P(vp)], st),
         "kct_plan_destroy": ([vp], st),
+        "kct_plan_reserve": ([vp, i32], st),
+        "kct_plan_check": ([vp, vp], st),
         "kct_plan_device_bytes": ([vp, P(sz)], st),
         "kct_forward": ([vp, vp, i32, vp, i32, vp], st),
         "kct_backproject": ([vp, vp, i32, vp, i32, vp], st),
@@ -101,7 +104,6 @@ def load(path: str = LIB_PATH):
         "kct_status_str": ([st], ctypes.c_char_p),
         "kct_last_error": ([], ctypes.c_char_p),
         "kct_version": ([], ctypes.c_char_p),
-        "kct_debug_take_error_flag": ([vp], ctypes.c_int),
         "kct_debug_bwd_shape": ([vp, P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_int)], None),
         "kct_debug_fwd_shape_geom": ([P(KctGeometry), P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_int),
                                       P(ctypes.c_int)], ctypes.c_int),

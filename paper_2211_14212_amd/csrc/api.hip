@@ -237,12 +237,60 @@ kct_status kct_plan_create(const kct_geometry *geom, int device, kct_plan **out)
     if (s == KCT_OK) s = launch_ray_lengths(*p, ts);
     if (s == KCT_OK) s = check_hip(hipStreamSynchronize(ts), "plan table build");
     if (ts) (void)hipStreamDestroy(ts);
+    // Partial volumes of the angle-split back projection (small volumes
+    // only, at most 16 x 2^18 floats without the KCT_BWD_SPLIT override), so
+    // that kct_backproject only enqueues.
+    if (s == KCT_OK && bwd_split_floats(*p) > 0) {
+        const size_t need = sizeof(float) * size_t(bwd_split_floats(*p));
+        s = check_hip(hipMalloc(&p->d_split, need), "partial volume allocation");
+        if (s == KCT_OK) p->split_bytes = need;
+    }
     if (s != KCT_OK) {
         kct_plan_destroy(p);
         return s;
     }
     *out = p;
     return KCT_OK;
+}
+
+kct_status kct_plan_reserve(kct_plan *p, int32_t vol_dtype)
+{
+    g_last_error.clear();
+    if (!p) return fail(KCT_E_INVALID_ARG, "plan is NULL");
+    if (!dtype_ok(vol_dtype)) return fail(KCT_E_DTYPE, "unknown storage type");
+    const size_t need = size_t(2 * p->pad.vox) * dtype_size(fwd_pad_dtype(*p, vol_dtype));
+    if (p->pad_bytes >= need) return KCT_OK;
+    DeviceGuard dg(p->device);
+    // The old copies may still be read by enqueued forward projections.
+    if (p->d_pad) {
+        kct_status s = check_hip(hipDeviceSynchronize(), "wait before replacing the padded copies");
+        if (s != KCT_OK) return s;
+        (void)hipFree(p->d_pad);
+    }
+    p->d_pad = nullptr;
+    p->pad_bytes = 0;
+    kct_status s = check_hip(hipMalloc(&p->d_pad, need), "padded volume allocation");
+    if (s != KCT_OK) return s;
+    p->pad_bytes = need;
+    return KCT_OK;
+}
+
+kct_status kct_plan_check(kct_plan *p, void *stream)
+{
+    g_last_error.clear();
+    if (!p) return fail(KCT_E_INVALID_ARG, "plan is NULL");
+    DeviceGuard dg(p->device);
+    kct_status s = check_hip(hipStreamSynchronize(static_cast<hipStream_t>(stream)), "stream synchronisation");
+    if (s != KCT_OK) return s;
+    int v = 0;
+    s = check_hip(hipMemcpy(&v, p->d_err, sizeof(int), hipMemcpyDeviceToHost), "error flag read");
+    if (s != KCT_OK) return s;
+    if (v == 0) return KCT_OK;
+    s = check_hip(hipMemset(p->d_err, 0, sizeof(int)), "error flag reset");
+    if (s != KCT_OK) return s;
+    return fail(KCT_E_GEOMETRY, std::string("a back projection met a voxel footprint wider than the plan's bound (") +
+                                    ((v & 1) ? "tile patch" : "") + ((v & 3) == 3 ? ", " : "") +
+                                    ((v & 2) ? "voxel columns" : "") + "): its sums are truncated");
 }
 
 kct_status kct_plan_destroy(kct_plan *p)
@@ -273,17 +321,12 @@ kct_status kct_forward(kct_plan *p, const void *d_vol, int32_t vol_dtype, void *
     g_last_error.clear();
     if (!p || !d_vol || !d_proj) return fail(KCT_E_INVALID_ARG, "NULL argument");
     if (!dtype_ok(vol_dtype) || !dtype_ok(proj_dtype)) return fail(KCT_E_DTYPE, "unknown storage type");
-    DeviceGuard dg(p->device);
     const int pdt = fwd_pad_dtype(*p, vol_dtype);
     const size_t need = size_t(2 * p->pad.vox) * dtype_size(pdt);
-    if (p->pad_bytes < need) {
-        if (p->d_pad) (void)hipFree(p->d_pad);
-        p->d_pad = nullptr;
-        p->pad_bytes = 0;
-        kct_status s = check_hip(hipMalloc(&p->d_pad, need), "padded volume allocation");
-        if (s != KCT_OK) return s;
-        p->pad_bytes = need;
-    }
+    if (p->pad_bytes < need)
+        return fail(KCT_E_BUDGET, "the plan holds no padded copies for this volume storage type: call "
+                                  "kct_plan_reserve(plan, vol_dtype) first");
+    DeviceGuard dg(p->device);
     hipStream_t st = static_cast<hipStream_t>(stream);
     kct_status s = launch_pad_volume_as(*p, d_vol, vol_dtype, pdt, p->d_pad, st);
     if (s != KCT_OK) return s;
@@ -300,16 +343,7 @@ kct_status kct_backproject(kct_plan *p, const void *d_proj, int32_t proj_dtype, 
     DeviceGuard dg(p->device);
     Epilogue ep;
     // Partial volumes of the angle-split back projection (small volumes),
-    // owned by the plan like the forward's padded copies.
-    const size_t need = sizeof(float) * size_t(bwd_split_floats(*p));
-    if (p->split_bytes < need) {
-        if (p->d_split) (void)hipFree(p->d_split);
-        p->d_split = nullptr;
-        p->split_bytes = 0;
-        kct_status s = check_hip(hipMalloc(&p->d_split, need), "partial volume allocation");
-        if (s != KCT_OK) return s;
-        p->split_bytes = need;
-    }
+    // allocated with the plan.
     ep.split = p->d_split;
     return launch_backward(*p, d_proj, proj_dtype, d_vol, vol_dtype, ep, static_cast<hipStream_t>(stream));
 }
@@ -325,21 +359,7 @@ kct_status kct_backproject_interp(kct_plan *p, const void *d_proj, int32_t proj_
     return launch_interp_backward(*p, d_proj, proj_dtype, d_vol, vol_dtype, ep, static_cast<hipStream_t>(stream));
 }
 
-// Test hook (not in kct.h): read and clear the back projector's footprint
-// overflow flag.  Synchronises the device.
-int kct_debug_take_error_flag(kct_plan *p)
-{
-    if (!p) return -1;
-    DeviceGuard dg(p->device);
-    int v = 0;
-    if (hipDeviceSynchronize() != hipSuccess) return -1;
-    if (hipMemcpy(&v, p->d_err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return -1;
-    (void)hipMemset(p->d_err, 0, sizeof(int));
-    return v;
-}
-
-// Test hook: the back projector launch shape a plan for `geom` would use,
-// computed on the host without touching a device.  Returns a kct_status.
+// Test hooks, declared in kct.h.
 int kct_debug_bwd_shape_geom(const kct_geometry *geom, int *kz, int *ncmax, int *pw, int *ph)
 {
     kct_status s = validate(geom);
@@ -358,8 +378,6 @@ int kct_debug_bwd_shape_geom(const kct_geometry *geom, int *kz, int *ncmax, int 
     return KCT_OK;
 }
 
-// Test hook: the forward launch shape a plan for `geom` would use, computed
-// on the host without touching a device.  Returns a kct_status.
 int kct_debug_fwd_shape_geom(const kct_geometry *geom, int *lane_u, int *wave_angles, int *angle_block, int *pad_f32)
 {
     kct_status s = validate(geom);
@@ -377,7 +395,6 @@ int kct_debug_fwd_shape_geom(const kct_geometry *geom, int *lane_u, int *wave_an
     return KCT_OK;
 }
 
-// Test hook: the back projector launch shape chosen for the plan.
 void kct_debug_bwd_shape(const kct_plan *p, int *kz, int *ncmax, int *pw, int *ph)
 {
     if (!p) return;

@@ -369,7 +369,7 @@ __global__ void k_sc_fl_hist(double *S, const double *M, int k, int ldm, double 
         h[0] = 0.0;
         h[1] = live ? S[S_FL_TKK] : 0.0;
         h[2] = live ? M[int64_t(k) * ldm + k + 1] : 0.0;
-        h[3] = S[S_DONE];
+        h[3] = hist_code(S);
         h[4] = S[S_HLAM];
     }
     S[S_HROW] = double(row + 1);

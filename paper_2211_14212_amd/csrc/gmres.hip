@@ -160,7 +160,7 @@ __global__ void k_sc_gm_givens(double *S, double *H, double *cs, double *sn, dou
             o[0] = kk > 0 ? fabs(g[kk]) : S[S_BETA];
             o[1] = sub;
             o[2] = diag;
-            o[3] = S[S_DONE];
+            o[3] = hist_code(S);
             o[4] = 0.0;
         }
     }

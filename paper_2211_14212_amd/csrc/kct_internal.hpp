@@ -83,6 +83,8 @@ enum ScalarIdx : int {
     S_DONE, S_ITER, S_HROW, S_KGK, S_RES,
     S_HLAM,                        // lambda reported in history column 4
     S_PREV_EXPL,                   // last explicit residual (stop rule; < 0 before the first)
+    S_ERR,                         // 1 once a back projection of this run met a footprint
+                                   // wider than the plan's bound (history code 4)
     // Coefficients the scalar kernels leave for the next vector kernels:
     S_F0 = 24, S_F1,               // forward projector epilogue (2)
     S_B0, S_B1, S_B2, S_B3,        // back projector epilogue (4)
@@ -101,13 +103,13 @@ struct Plan {
     AngleGeo *d_tab = nullptr;   // per-angle table
     double *d_invv = nullptr;    // 1/v per detector row (0 where v == 0)
     float *d_dlen = nullptr;     // |pixel centre - source| (mm) per detector pixel, [nv][nu]
-    void *d_pad = nullptr;       // padded volume copies for plain kct_forward calls
+    void *d_pad = nullptr;       // padded volume copies for plain kct_forward calls (kct_plan_reserve)
     size_t pad_bytes = 0;        // capacity of d_pad
     int *d_err = nullptr;         // back projector footprint overflow flag (0 = fine)
     // Back projector launch shape (chosen from the geometry at plan creation).
     int bwd_kz = 8, bwd_ncmax = 5, bwd_pw = 0, bwd_ph = 0, bwd_fp_angles = 0;
     int bwd_asplit = 1;           // angle chunks of the back projector (small volumes: > 1)
-    float *d_split = nullptr;     // partial volumes for plain kct_backproject calls
+    float *d_split = nullptr;     // partial volumes for plain kct_backproject calls (at plan creation)
     size_t split_bytes = 0;       // capacity of d_split
     bool fwd_prefetch = true;     // forward projector gathers one segment ahead
     int fwd_lane_u = 16;          // forward wave patch: lane_u x (64 / lane_u) rays (64, 32 or 16)
@@ -133,7 +135,12 @@ struct Epilogue {
     const void *in3 = nullptr;    // same storage type as out
     double *partials = nullptr;   // per-workgroup sum of out^2, or null
     float *split = nullptr;       // back projector: bwd_split_floats(plan) floats of partial volumes
+    double *err_scal = nullptr;   // back projector: scalar block whose S_ERR records a footprint overflow
 };
+
+// Done code a history row records: 4 when a back projection of the run met a
+// footprint wider than the plan's bound, else the solver's own S_DONE code.
+__device__ inline double hist_code(const double *S) { return S[S_ERR] != 0.0 ? 4.0 : S[S_DONE]; }
 
 // Thread-local error text.
 void set_error(const std::string &msg);

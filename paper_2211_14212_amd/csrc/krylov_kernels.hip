@@ -172,7 +172,7 @@ __device__ inline void write_hist(double *hist, double *S, double res, double a,
             h[0] = res;
             h[1] = a;
             h[2] = b;
-            h[3] = S[S_DONE];
+            h[3] = hist_code(S);
             h[4] = S[S_HLAM];
         }
     }
@@ -498,7 +498,7 @@ __global__ __launch_bounds__(256) void k_sc_explicit(double *S, const double *p,
         const int64_t row = int64_t(S[S_HROW]) - 1;
         if (row >= 0 && row < int64_t(S[S_ITER])) {
             hist[row * KCT_HIST_COLS + 0] = r;
-            hist[row * KCT_HIST_COLS + 3] = S[S_DONE];
+            hist[row * KCT_HIST_COLS + 3] = hist_code(S);
         }
     }
 }

@@ -176,7 +176,13 @@ __global__ __launch_bounds__(256) void k_backward(const TP *__restrict__ proj, T
         int pw = iu_hi - iu_lo + 1, ph = f.iv_hi - iv_lo + 1;
         if (pw <= 0 || ph <= 0) continue;
         if (pw > pw_max || ph > ph_max) {
-            if (threadIdx.x == 0 && err_flag) atomicOr(err_flag, 1);
+            // Never expected (the plan's bounds come from the extreme
+            // magnification): the sums are truncated, and the caller learns
+            // it from kct_plan_check or history code 4.
+            if (threadIdx.x == 0) {
+                if (err_flag) atomicOr(err_flag, 1);
+                if (ep.err_scal) ep.err_scal[S_ERR] = 1.0;
+            }
             pw = min(pw, pw_max);
             ph = min(ph, ph_max);
         }
@@ -229,8 +235,9 @@ __global__ __launch_bounds__(256) void k_backward(const TP *__restrict__ proj, T
             }
             const int c_lo = max(iu_lo, int(ceilf(cumin * idu + cu - margin)));
             int nc = min(iu_hi, int(floorf(cumax * idu + cu + margin))) - c_lo + 1;
-            if (nc > NCM) {
+            if (nc > NCM) { // never expected either; reported like the patch overflow
                 if (err_flag) atomicOr(err_flag, 2);
+                if (ep.err_scal) ep.err_scal[S_ERR] = 1.0;
                 nc = NCM;
             }
             nc = min(nc, pw - (c_lo - iu_lo)); // stay inside the staged patch
@@ -571,8 +578,16 @@ kct_status choose_bwd_shape(Plan &p)
                                      0.02) + 2.0;
         p.bwd_pw = int(std::min<double>(pw, g.nu));
         p.bwd_ph = int(std::min<double>(ph, g.nv));
+        // Test hook: a smaller patch-width bound, to exercise the overflow
+        // report (every access still stays inside the smaller patch).
+        if (const char *e = std::getenv("KCT_BWD_TEST_PW_MAX")) {
+            const int v = std::atoi(e);
+            if (v >= 1) p.bwd_pw = std::min(p.bwd_pw, v);
+        }
+        // The patch is followed by NCM zeros that the unrolled column loop
+        // may read past its last row.
         p.bwd_lds = size_t(p.bwd_pw) * 16 + size_t(p.bwd_ph) * 8 + size_t(p.bwd_fp_angles) * 16 +
-                    (size_t(p.bwd_pw) * p.bwd_ph + 8) * sizeof(float);
+                    (size_t(p.bwd_pw) * p.bwd_ph + size_t(p.bwd_ncmax)) * sizeof(float);
         if (p.bwd_lds + size_t(p.bwd_kz) * 256 * sizeof(float) <= 64 * 1024) {
             choose_bwd_split(p);
             return KCT_OK;

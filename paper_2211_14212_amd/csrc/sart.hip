@@ -86,7 +86,7 @@ __global__ __launch_bounds__(256) void k_sc_sart_res(double *S, const double *p,
                 h[0] = sqrt(S[S_RES]);
                 h[1] = 0.0;
                 h[2] = 0.0;
-                h[3] = S[S_DONE];
+                h[3] = hist_code(S);
                 h[4] = S[S_HLAM];
             }
         }

@@ -299,6 +299,7 @@ Reduced red(const kct_state &s, const double *parts, int64_t n, int slot)
 kct_status backward_into(kct_state &s, Plan &p, const void *proj, int pdt, void *vol, int vdt, Epilogue ep)
 {
     ep.split = reinterpret_cast<float *>(s.ws + s.L.bsplit);
+    ep.err_scal = s.S(); // a footprint overflow becomes history code 4
     return launch_backward(p, proj, pdt, vol, vdt, ep, s.st);
 }
 
@@ -809,6 +810,9 @@ kct_status fl_iter(kct_state &s)
 
 kct_status enqueue_init(kct_state &s)
 {
+    // S_ERR (one double) starts at 0: a fill kernel, not a memset, so that
+    // the start can be captured into a graph.
+    KCT_TRY(vk_fill(s.S() + S_ERR, KCT_F32, 2, 0.f, s.st));
     switch (s.prm.solver) {
     case KCT_CGLS: return cgls_init(s);
     case KCT_LSQR: return lsqr_init(s);

@@ -53,7 +53,7 @@ def test_projectors_on_degenerate_shapes(kct, name):
           flush=True)
     assert np.count_nonzero(rf) > 0
     assert _rel(gf, rf) <= 1e-6 and _rel(gb, rb) <= 1e-6
-    assert kct._lib.load().kct_debug_take_error_flag(plan.handle) == 0
+    plan.check()  # no footprint beyond the plan's bounds
 
 
 @pytest.mark.parametrize("solver,kw", [("cgls", {}), ("lsqr", {}), ("lsmr", {}), ("hybrid_lsqr", {}),
@@ -83,3 +83,31 @@ def test_irn_tv_single_inner_step(kct):
     ref, _ = S.irn_tv_cgls(lambda v: oracle.forward(og, v), lambda y: oracle.adjoint(og, y), b.astype(np.float64),
                            og.vol_shape, 1, 1, 0.5, 1e-3)
     assert _rel(x.cpu().numpy(), ref) <= 1e-5
+
+
+def test_footprint_overflow_is_reported(kct, monkeypatch):
+    """A back projection whose footprint exceeds the plan's bound never passes
+    silently.  The overflow is forced from the host (a patch-width bound of 2
+    columns, far below this geometry's 13); every access stays inside the
+    smaller patch.  kct_plan_check then fails and a solve records code 4."""
+    gd = synth.geometry(dict(nx=24, ny=24, nz=8, vx=1.0, vy=1.0, vz=1.0, nu=48, nv=16, du=1.0, dv=1.0, dso=80.0,
+                             dsd=120.0, n_angles=6))
+    kg = kct.Geometry.from_dict(gd)
+    y = torch.from_numpy(synth.random_projections(kg.proj_shape, 9)).to(DEV)
+    clean = kct.Plan(kg)
+    clean.backproject(y)
+    clean.check()
+    _, h = clean.solve(y, "cgls", 3)
+    assert torch.count_nonzero(h[:, 3]) == 0
+    monkeypatch.setenv("KCT_BWD_TEST_PW_MAX", "2")
+    plan = kct.Plan(kg)
+    plan.backproject(y)
+    with pytest.raises(kct.KctError) as err:
+        plan.check()
+    assert err.value.name == "KCT_E_GEOMETRY"
+    plan.check()  # the flag was cleared by the failing check
+    for solver in ("cgls", "lsqr"):
+        _, h = plan.solve(y, solver, 3)
+        assert torch.all(h[:, 3] == 4.0), (solver, h[:, 3])
+    with pytest.raises(kct.KctError):
+        plan.check()
