@@ -122,6 +122,10 @@ typedef struct kct_plan kct_plan;
  *   KCT_BWD_ACC          0 or 1   back-projector sums in registers or LDS (1)
  *   KCT_BWD_SPLIT        1..16    angle chunks of the back projection
  *                                 (more than 1 only for small volumes)
+ *   KCT_BWD_RAYS         0 or 1   the ray-driven back projector (1 wherever
+ *                                 every voxel's footprint is narrower than a
+ *                                 pixel, which it needs; 1 is ignored
+ *                                 elsewhere) or the voxel-driven one
  *   KCT_BWD_TEST_PW_MAX  >= 1     test hook: caps the back projector's per-tile
  *                                 patch width, so that the footprint overflow
  *                                 report (kct_plan_check, history code 4) can
@@ -411,6 +415,16 @@ int kct_debug_fwd_shape_geom(const kct_geometry *geom, int *lane_u, int *wave_an
 
 /* The back projector's shape of an existing plan (as kct_debug_bwd_shape_geom). */
 void kct_debug_bwd_shape(const kct_plan *plan, int *kz, int *ncmax, int *pw, int *ph);
+
+/* Which back projector the plan logic picks for `geom`, without touching a
+ * device: the number of angle chunks (1, or up to 16 for small volumes) and
+ * whether the ray-driven kernel runs (1: every voxel's footprint is narrower
+ * than one pixel, so rays are walked through voxel tiles) or the
+ * voxel-driven one (0).  Any output may be NULL.  Returns a kct_status. */
+int kct_debug_bwd_mode_geom(const kct_geometry *geom, int *split, int *rays);
+
+/* The same for an existing plan. */
+void kct_debug_bwd_mode(const kct_plan *plan, int *split, int *rays);
 
 #ifdef __cplusplus
 }

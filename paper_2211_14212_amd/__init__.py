@@ -159,6 +159,14 @@ class Plan:
         with torch.cuda.device(self.device):
             _lib.check(_lib.load().kct_plan_check(self._h, _stream_ptr(stream)), "kct_plan_check")
 
+    def bwd_shape(self) -> dict:
+        """The back projector's launch shape this plan chose (test hooks)."""
+        kz, nc, pw, ph, split, rays = (ctypes.c_int() for _ in range(6))
+        lib = _lib.load()
+        lib.kct_debug_bwd_shape(self._h, ctypes.byref(kz), ctypes.byref(nc), ctypes.byref(pw), ctypes.byref(ph))
+        lib.kct_debug_bwd_mode(self._h, ctypes.byref(split), ctypes.byref(rays))
+        return dict(kz=kz.value, ncmax=nc.value, pw=pw.value, ph=ph.value, split=split.value, rays=rays.value)
+
     def device_bytes(self) -> int:
         n = ctypes.c_size_t()
         _lib.check(_lib.load().kct_plan_device_bytes(self._h, ctypes.byref(n)), "kct_plan_device_bytes")

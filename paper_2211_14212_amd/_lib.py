@@ -109,6 +109,8 @@ def load(path: str = LIB_PATH):
                                       P(ctypes.c_int)], ctypes.c_int),
         "kct_debug_bwd_shape_geom": ([P(KctGeometry), P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_int),
                                       P(ctypes.c_int)], ctypes.c_int),
+        "kct_debug_bwd_mode_geom": ([P(KctGeometry), P(ctypes.c_int), P(ctypes.c_int)], ctypes.c_int),
+        "kct_debug_bwd_mode": ([vp, P(ctypes.c_int), P(ctypes.c_int)], None),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

@@ -395,6 +395,29 @@ int kct_debug_fwd_shape_geom(const kct_geometry *geom, int *lane_u, int *wave_an
     return KCT_OK;
 }
 
+int kct_debug_bwd_mode_geom(const kct_geometry *geom, int *split, int *rays)
+{
+    kct_status s = validate(geom);
+    if (s != KCT_OK) return s;
+    Plan p;
+    p.geom = *geom;
+    p.angles.assign(geom->angles, geom->angles + geom->n_angles);
+    p.geom.angles = p.angles.data();
+    build_tables(p);
+    s = choose_bwd_shape(p);
+    if (s != KCT_OK) return s;
+    if (split) *split = std::min(p.bwd_asplit, p.gp.na);
+    if (rays) *rays = p.bwd_rays ? 1 : 0;
+    return KCT_OK;
+}
+
+void kct_debug_bwd_mode(const kct_plan *p, int *split, int *rays)
+{
+    if (!p) return;
+    if (split) *split = std::min(p->bwd_asplit, p->gp.na);
+    if (rays) *rays = p->bwd_rays ? 1 : 0;
+}
+
 void kct_debug_bwd_shape(const kct_plan *p, int *kz, int *ncmax, int *pw, int *ph)
 {
     if (!p) return;

@@ -117,6 +117,8 @@ struct Plan {
     int fwd_angle_block = 8;      // forward work order: angles per block (4, 8, 16 or 32)
     bool fwd_pad_f32 = true;      // forward: 16-bit volumes are padded into FP32 copies (small volumes)
     bool bwd_acc_lds = true;      // back projector keeps per-voxel sums in LDS
+    bool bwd_sparse_ok = false;   // every voxel footprint narrower than a pixel (u and v)
+    bool bwd_rays = false;        // ray-driven back projector (needs bwd_sparse_ok)
     size_t bwd_lds = 0;
     int64_t n_vox() const { return int64_t(gp.nx) * gp.ny * gp.nz; }
     int64_t n_ray() const { return int64_t(gp.na) * gp.nv * gp.nu; }

@@ -21,6 +21,23 @@
 // staged value.  A workgroup is a 16 x 16 x KZ voxel tile; per angle it stages
 // the tile's detector footprint (values pre-multiplied by the ray length |d|)
 // and the per-column 1/dx, 1/dy and per-row 1/v in LDS.
+//
+// Sparse rays (k_backward_rays).  When the detector samples the volume more
+// coarsely than the voxel grid (micro-CT: 0.37 nonzeros per voxel-view), most
+// voxel-views hold no nonzero and the per-voxel candidate search above costs
+// far more than the sums.  If every voxel's footprint is narrower than one
+// pixel along u and along v (checked on the host from the extreme
+// magnification), at most one ray of an angle meets any voxel.  The kernel
+// then walks rays instead: a workgroup owns a 16 x 16 x 8 voxel tile with its
+// sums in LDS, and its lanes trace the rays of the tile's footprint through
+// the tile, adding length * value to the voxels they cross.  Rays of one
+// angle never share a voxel, so a lane's read-add-write of a voxel sum meets
+// no other lane's.  Up to four consecutive angles run side by side, each
+// into its own copy of the tile sums, and a barrier separates these passes,
+// so every sum receives its terms in a fixed order (angle order within a
+// copy, then the four copies added in order): the result is deterministic
+// and needs no atomics.  Lengths come from the same FP64 slab-crossing walk
+// as the forward projector's.
 
 #include "kct_internal.hpp"
 
@@ -378,6 +395,207 @@ __global__ __launch_bounds__(256) void k_backward(const TP *__restrict__ proj, T
     }
 }
 
+// ---------------------------------------------------------------------------
+// Ray-driven back projection for sparse rays (see the top of this file).
+// ---------------------------------------------------------------------------
+constexpr int BR_TX = 16, BR_TY = 16, BR_TZ = 8;     // voxel tile
+constexpr int BR_VOX = BR_TX * BR_TY * BR_TZ;        // 2048 sums per copy
+constexpr int BR_COPIES = 4;                         // angles side by side
+constexpr int BR_FP = 64;                            // tile footprints kept in LDS at a time
+// Segments shorter than this (in units of the whole source-pixel ray) are
+// skipped.  The walk's crossings carry ~1e-15 rounding; where a crossing
+// rounds to just before the tile's exit, the walk takes one extra step out of
+// the tile, onto a segment no longer than that rounding, which must not be
+// written.  A real segment this short weighs 1e-12 of a ray (~1e-9 mm).
+constexpr double BR_MIN_LEN = 1.0e-12;
+
+// 0.0 or 1.0 from a predicate, built from the high word only (one select).
+__device__ inline double br_one_if(bool c)
+{
+    return __builtin_bit_cast(double, uint64_t(c ? 0x3ff00000u : 0u) << 32);
+}
+
+template <typename TP, typename TV>
+__global__ __launch_bounds__(256) void k_backward_rays(const TP *__restrict__ proj, TV *__restrict__ vol,
+                                                       const AngleGeo *__restrict__ tab,
+                                                       const double *__restrict__ invv,
+                                                       const float *__restrict__ dlen, GeoParams g, int tiles_x,
+                                                       int tiles_y, int64_t groups, Epilogue ep)
+{
+    const int chunks = int(gridDim.y), chunk = int(blockIdx.y);
+    const int a_begin = int(int64_t(g.na) * chunk / chunks), a_end = int(int64_t(g.na) * (chunk + 1) / chunks);
+    __shared__ float sums[BR_COPIES][BR_VOX];
+    __shared__ int4 fps[BR_FP];
+    __shared__ double red[4];
+
+    const int64_t g8 = (groups + 7) / 8;
+    const int64_t b = blockIdx.x;
+    const int64_t logical = (b & 7) * g8 + (b >> 3);
+    if (logical >= groups) return;
+    if (ep.scal && ep.scal[S_DONE] != 0.0) return;
+
+    double c0 = ep.c[0], c1 = ep.c[1], c2 = ep.c[2], c3 = ep.c[3];
+    if (ep.coef_idx >= 0) {
+        c0 = ep.scal[ep.coef_idx];
+        c1 = ep.scal[ep.coef_idx + 1];
+        c2 = ep.scal[ep.coef_idx + 2];
+        c3 = ep.scal[ep.coef_idx + 3];
+    }
+
+    const int per_z = tiles_x * tiles_y;
+    const int tz = int(logical / per_z);
+    const int rem = int(logical - int64_t(tz) * per_z);
+    const int tyi = rem / tiles_x, txi = rem - tyi * tiles_x;
+    const int i0 = txi * BR_TX, j0 = tyi * BR_TY, k0 = tz * BR_TZ;
+    const int ie = min(i0 + BR_TX, g.nx), je = min(j0 + BR_TY, g.ny), ke = min(k0 + BR_TZ, g.nz);
+    const float tx0 = float(g.X0 + i0 * g.vx), tx1 = float(g.X0 + ie * g.vx);
+    const float ty0 = float(g.Y0 + j0 * g.vy), ty1 = float(g.Y0 + je * g.vy);
+    const float tz0 = float(g.Z0 + k0 * g.vz), tz1 = float(g.Z0 + ke * g.vz);
+    const float margin = 0.01f; // pixels: the footprint only enumerates candidate rays
+
+    for (int e = threadIdx.x; e < BR_COPIES * BR_VOX; e += 256) (&sums[0][0])[e] = 0.f;
+
+    for (int cb = a_begin; cb < a_end; cb += BR_FP) {
+        const int ce = min(cb + BR_FP, a_end);
+        __syncthreads(); // the previous chunk's footprints are no longer read
+        if (threadIdx.x < ce - cb) {
+            const Footprint f = tile_footprint(tab[cb + threadIdx.x], g, tx0, tx1, ty0, ty1, tz0, tz1, margin);
+            fps[threadIdx.x] = make_int4(f.iu_lo, f.iu_hi, f.iv_lo, f.iv_hi);
+        }
+        __syncthreads();
+        for (int a = cb; a < ce;) {
+            // Pack up to BR_COPIES consecutive angles whose footprints hold at
+            // most 256 rays together (a larger single footprint takes a pass
+            // of its own, in rounds of 256).  Uniform over the workgroup.
+            int pre1 = 1 << 30, pre2 = 1 << 30, pre3 = 1 << 30, tot = 0, m = 0;
+#pragma unroll
+            for (int q = 0; q < BR_COPIES; ++q) {
+                if (a + q >= ce) break;
+                const int4 f = fps[a + q - cb];
+                const int n = max(0, f.y - f.x + 1) * max(0, f.w - f.z + 1);
+                if (q > 0 && tot + n > 256) break;
+                if (q == 1) pre1 = tot;
+                if (q == 2) pre2 = tot;
+                if (q == 3) pre3 = tot;
+                tot += n;
+                m = q + 1;
+            }
+            for (int t = threadIdx.x; t < tot; t += 256) {
+                const int q = int(t >= pre1) + int(t >= pre2) + int(t >= pre3);
+                const int qs = q == 0 ? 0 : (q == 1 ? pre1 : (q == 2 ? pre2 : pre3));
+                const int aa = a + q;
+                const int4 f = fps[aa - cb];
+                const int pw = f.y - f.x + 1;
+                const int e = t - qs;
+                const int r = int((float(e) + 0.5f) * __builtin_amdgcn_rcpf(float(pw)));
+                const int iu = f.x + (e - r * pw), iv = f.z + r;
+                const int64_t pix = int64_t(iv) * g.nu + iu;
+                const float yv = to_f32(proj[int64_t(aa) * g.nv * g.nu + pix]) * dlen[pix];
+                if (yv == 0.f) continue;
+                float *acc = sums[(aa - a_begin) % BR_COPIES];
+
+                // The ray from the source to the pixel centre, in the voxel
+                // frame (voxel (i,j,k) = [i,i+1) x [j,j+1) x [k,k+1)), clipped
+                // to the tile.
+                const AngleGeo A = tab[aa];
+                const double u = (iu - g.cu) * g.du, v = (iv - g.cv) * g.dv;
+                const double dx = A.d0x + u * A.eux, dy = A.d0y + u * A.euy, dz = v * g.ivz;
+                double tmin = 0.0, tmax = 1.0, inx = 0.0, iny = 0.0, inz = 0.0;
+                if (dx != 0.0) {
+                    inx = 1.0 / dx;
+                    const double ta = (double(i0) - A.svx) * inx, tb = (double(ie) - A.svx) * inx;
+                    tmin = fmax(tmin, fmin(ta, tb));
+                    tmax = fmin(tmax, fmax(ta, tb));
+                } else if (!(A.svx >= i0 && A.svx < ie)) {
+                    continue;
+                }
+                if (dy != 0.0) {
+                    iny = 1.0 / dy;
+                    const double ta = (double(j0) - A.svy) * iny, tb = (double(je) - A.svy) * iny;
+                    tmin = fmax(tmin, fmin(ta, tb));
+                    tmax = fmin(tmax, fmax(ta, tb));
+                } else if (!(A.svy >= j0 && A.svy < je)) {
+                    continue;
+                }
+                if (dz != 0.0) {
+                    // 1/dz = vz / v (the per-row table holds 1/v).
+                    inz = g.vz * invv[iv];
+                    const double ta = (double(k0) - A.svz) * inz, tb = (double(ke) - A.svz) * inz;
+                    tmin = fmax(tmin, fmin(ta, tb));
+                    tmax = fmin(tmax, fmax(ta, tb));
+                } else if (!(A.svz >= k0 && A.svz < ke)) {
+                    continue;
+                }
+                if (!(tmin < tmax)) continue;
+                const int i = min(max(int(floor(A.svx + tmin * dx)), i0), ie - 1);
+                const int j = min(max(int(floor(A.svy + tmin * dy)), j0), je - 1);
+                const int k = min(max(int(floor(A.svz + tmin * dz)), k0), ke - 1);
+                constexpr double FAR = 1.0e300;
+                double txc = FAR, tyc = FAR, tzc = FAR, dtx = 0.0, dty = 0.0, dtz = 0.0;
+                int sx = 0, sy = 0, sz = 0;
+                if (dx > 0.0) { txc = (i + 1 - A.svx) * inx; dtx = inx; sx = 1; }
+                else if (dx < 0.0) { txc = (i - A.svx) * inx; dtx = -inx; sx = -1; }
+                if (dy > 0.0) { tyc = (j + 1 - A.svy) * iny; dty = iny; sy = BR_TX; }
+                else if (dy < 0.0) { tyc = (j - A.svy) * iny; dty = -iny; sy = -BR_TX; }
+                if (dz > 0.0) { tzc = (k + 1 - A.svz) * inz; dtz = inz; sz = BR_TX * BR_TY; }
+                else if (dz < 0.0) { tzc = (k - A.svz) * inz; dtz = -inz; sz = -BR_TX * BR_TY; }
+                int off = ((k - k0) * BR_TY + (j - j0)) * BR_TX + (i - i0);
+                double tc = tmin;
+                // Each step ends the current segment at the first crossing
+                // (or the exit) and advances exactly one axis, x before y
+                // before z on ties (a tie leaves a zero-length segment in a
+                // diagonal neighbour, which is skipped).  While t < tmax the
+                // walk stays inside the tile, so every written index is one
+                // of the tile's voxels; at most nx+ny+nz+3 steps.
+                for (;;) {
+                    const double m1 = fmin(txc, tyc);
+                    const double t1 = fmin(m1, tzc);
+                    const double tn = fmin(t1, tmax);
+                    const double len = tn - tc;
+                    if (len > BR_MIN_LEN) acc[off] = fmaf(float(len), yv, acc[off]);
+                    if (!(t1 < tmax)) break;
+                    const bool xy = txc <= tyc, first = m1 <= tzc;
+                    txc = fma(br_one_if(xy && first), dtx, txc);
+                    tyc = fma(br_one_if(!xy && first), dty, tyc);
+                    tzc = fma(br_one_if(!first), dtz, tzc);
+                    off += first ? (xy ? sx : sy) : sz;
+                    tc = t1;
+                }
+            }
+            __syncthreads(); // this pass's sums are complete before its copies take the next angles
+            a += m;
+        }
+    }
+    __syncthreads();
+
+    // Add the copies in order and apply the epilogue (or, with an angle
+    // split, store this chunk's raw sums).
+    double part = 0.0;
+    for (int l = threadIdx.x; l < BR_VOX; l += 256) {
+        const int li = l % BR_TX, lj = (l / BR_TX) % BR_TY, lk = l / (BR_TX * BR_TY);
+        const int i = i0 + li, j = j0 + lj, k = k0 + lk;
+        if (i >= ie || j >= je || k >= ke) continue;
+        const float a_k = ((sums[0][l] + sums[1][l]) + sums[2][l]) + sums[3][l];
+        const int64_t idx = (int64_t(k) * g.ny + j) * g.nx + i;
+        if (chunks > 1) {
+            ep.split[int64_t(chunk) * g.nx * g.ny * g.nz + idx] = a_k;
+            continue;
+        }
+        double o = c0 * double(a_k);
+        if (ep.in1 && c1 != 0.0) o += c1 * double(to_f32(static_cast<const TV *>(ep.in1)[idx]));
+        if (ep.in2 && c2 != 0.0) o += c2 * double(ep.in2[idx]);
+        if (ep.in3 && c3 != 0.0) o += c3 * double(to_f32(static_cast<const TV *>(ep.in3)[idx]));
+        const TV st = from_f32<TV>(float(o));
+        vol[idx] = st;
+        const double sv = double(to_f32(st));
+        part += sv * sv;
+    }
+    if (chunks == 1 && ep.partials) {
+        const double sres = block_sum_256b(part, red);
+        if (threadIdx.x == 0) ep.partials[logical] = sres;
+    }
+}
+
 // Sum of the angle chunks' partial volumes in chunk order, then the epilogue
 // of k_backward (out = c0 sum + c1 in1 + c2 in2 + c3 in3, partial sums of
 // out^2 per workgroup).
@@ -423,10 +641,12 @@ struct BwdShape {
 
 BwdShape bwd_shape(const Plan &p)
 {
+    static_assert(BR_TX == BWD_TX && BR_TY == BWD_TY, "both back projectors tile x and y alike");
+    const int tz = p.bwd_rays ? BR_TZ : p.bwd_kz;
     BwdShape s;
     s.tiles_x = (p.gp.nx + BWD_TX - 1) / BWD_TX;
     s.tiles_y = (p.gp.ny + BWD_TY - 1) / BWD_TY;
-    s.tiles_z = (p.gp.nz + p.bwd_kz - 1) / p.bwd_kz;
+    s.tiles_z = (p.gp.nz + tz - 1) / tz;
     s.groups = s.tiles_x * s.tiles_y * s.tiles_z;
     return s;
 }
@@ -489,8 +709,36 @@ kct_status bwd_launch2(Plan &p, const void *proj, void *vol, const Epilogue &ep,
 }
 
 template <typename TP, typename TV>
+kct_status bwd_rays_launch(Plan &p, const void *proj, void *vol, const Epilogue &ep, hipStream_t st)
+{
+    const BwdShape s = bwd_shape(p);
+    const int64_t launch = ((s.groups + 7) / 8) * 8;
+    const int chunks = std::min(p.bwd_asplit, p.gp.na);
+    if (launch * 256 * chunks >= (int64_t(1) << 32)) return fail(KCT_E_GEOMETRY, "back projection grid too large");
+    if (chunks > 1) {
+        if (!ep.split) return fail(KCT_E_INVALID_ARG, "internal: angle-split back projection without a buffer");
+        Epilogue raw = ep; // the combine kernel applies the epilogue
+        raw.partials = nullptr;
+        hipLaunchKernelGGL((k_backward_rays<TP, TV>), dim3(unsigned(launch), unsigned(chunks), 1u), dim3(256), 0, st,
+                           static_cast<const TP *>(proj), static_cast<TV *>(vol), p.d_tab, p.d_invv, p.d_dlen, p.gp,
+                           int(s.tiles_x), int(s.tiles_y), s.groups, raw);
+        const kct_status e = check_hip(hipGetLastError(), "back projection launch");
+        if (e != KCT_OK) return e;
+        const int64_t n = p.n_vox();
+        hipLaunchKernelGGL((k_bwd_combine<TV>), dim3(unsigned(combine_groups(n))), dim3(256), 0, st, ep.split,
+                           chunks, n, static_cast<TV *>(vol), ep);
+        return check_hip(hipGetLastError(), "back projection combine launch");
+    }
+    hipLaunchKernelGGL((k_backward_rays<TP, TV>), dim3(unsigned(launch)), dim3(256), 0, st,
+                       static_cast<const TP *>(proj), static_cast<TV *>(vol), p.d_tab, p.d_invv, p.d_dlen, p.gp,
+                       int(s.tiles_x), int(s.tiles_y), s.groups, ep);
+    return check_hip(hipGetLastError(), "back projection launch");
+}
+
+template <typename TP, typename TV>
 kct_status bwd_launch1(Plan &p, const void *proj, void *vol, const Epilogue &ep, hipStream_t st)
 {
+    if (p.bwd_rays) return bwd_rays_launch<TP, TV>(p, proj, vol, ep, st);
     if (p.bwd_kz == 16) return bwd_launch2<TP, TV, 16>(p, proj, vol, ep, st);
     if (p.bwd_kz == 8) return bwd_launch2<TP, TV, 8>(p, proj, vol, ep, st);
     return bwd_launch2<TP, TV, 1>(p, proj, vol, ep, st);
@@ -548,6 +796,19 @@ kct_status choose_bwd_shape(Plan &p)
         if (ncols <= c) { ncm = c; break; }
     if (!ncm) return fail(KCT_E_GEOMETRY, "voxels project onto more than 16 detector columns");
     p.bwd_ncmax = ncm;
+
+    // Sparse rays: every voxel's footprint narrower than one pixel along u
+    // (the column bound above, before its rounding up) and along v (the
+    // voxel's height at the nearest depth plus the slope of its farthest
+    // plane across its depth), with 2 % to spare.  Then no two rays of one
+    // angle meet a voxel, which the ray-driven kernel relies on.
+    const double u_width = vox_diag * mag / g.du;
+    const double v_height = g.dsd / wmin * (g.vz + zmax * vox_diag / wmin) / g.dv;
+    p.bwd_sparse_ok = u_width <= 0.98 && v_height <= 0.98;
+    p.bwd_rays = p.bwd_sparse_ok;
+    // Tuning override: KCT_BWD_RAYS=0 selects the voxel-driven kernel; 1 the
+    // ray-driven one, only where the geometry allows it.
+    if (const char *e = std::getenv("KCT_BWD_RAYS")) p.bwd_rays = std::atoi(e) != 0 && p.bwd_sparse_ok;
 
     // The deepest z run per thread (16, else 8 voxels) that still leaves
     // enough workgroups to fill 256 CUs several times over, with the per-voxel
