@@ -34,7 +34,7 @@ import math
 import numpy as np
 
 __all__ = ["angles", "workload", "geometry", "crop_geometry", "ellipsoid_phantom", "torso_phantom",
-           "porous_phantom", "phantom", "add_noise", "add_noise_torch", "random_volume", "random_projections",
+           "porous_phantom", "porous_phantom_torch", "phantom", "add_noise", "add_noise_torch", "random_volume", "random_projections",
            "serve_stream", "block_geometry", "WORKLOADS"]
 
 
@@ -203,11 +203,7 @@ def porous_phantom(g: dict, n: int, radius_vox, cyl_frac: float, blur_sigma: flo
     full_n = full_n or g["nx"]
     R = cyl_frac * full_n
     c0 = full_n / 2.0
-    pores = []
-    while len(pores) < n:
-        p = rng.uniform(0, full_n, 3)
-        if (p[0] - c0) ** 2 + (p[1] - c0) ** 2 <= R * R:
-            pores.append((p, rng.uniform(radius_vox[0], radius_vox[1])))
+    pores = _pores(rng, n, radius_vox, R, c0, full_n)
     pad = int(math.ceil(4 * blur_sigma)) + 1
     k0, j0, i0 = crop_origin
     shape = (g["nz"] + 2 * pad, g["ny"] + 2 * pad, g["nx"] + 2 * pad)
@@ -229,6 +225,79 @@ def porous_phantom(g: dict, n: int, radius_vox, cyl_frac: float, blur_sigma: flo
     if blur_sigma > 0:
         vol = gaussian_filter(vol, blur_sigma, mode="constant")
     return np.ascontiguousarray(vol[pad:-pad, pad:-pad, pad:-pad]).astype(np.float32)
+
+
+def _pores(rng, n, radius_vox, R, c0, full_n):
+    pores = []
+    while len(pores) < n:
+        p = rng.uniform(0, full_n, 3)
+        if (p[0] - c0) ** 2 + (p[1] - c0) ** 2 <= R * R:
+            pores.append((p, rng.uniform(radius_vox[0], radius_vox[1])))
+    return pores
+
+
+def porous_phantom_torch(g: dict, n: int, radius_vox, cyl_frac: float, blur_sigma: float, seed: int, device):
+    """``porous_phantom`` of the whole grid, built with torch on ``device``
+    (the 1500^3 volume takes minutes on the host).  Same pores (the same PCG64
+    draws), cylinder and blur: a truncated Gaussian of radius int(4 sigma + 0.5)
+    voxels, normalised, applied along each axis in turn with zeros outside the
+    grid, summed in FP64 as c0 x_i + sum_t c_t (x_{i+t} + x_{i-t}).  Equals
+    the host version to FP32 rounding; FP32 result on ``device``."""
+    import torch
+
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = g["nz"], g["ny"], g["nx"]
+    full_n = nx
+    R = cyl_frac * full_n
+    c0 = full_n / 2.0
+    pores = _pores(rng, n, radius_vox, R, c0, full_n)
+    ii = torch.arange(nx, device=device, dtype=torch.float64) + 0.5
+    jj = torch.arange(ny, device=device, dtype=torch.float64) + 0.5
+    kk = torch.arange(nz, device=device, dtype=torch.float64) + 0.5
+    cyl = ((ii[None, :] - c0) ** 2 + (jj[:, None] - c0) ** 2 <= R * R).to(torch.float32)
+    vol = cyl[None].expand(nz, ny, nx).contiguous()
+    for p, r in pores:
+        lo = [int(max(0, math.floor(p[a] - r))) for a in range(3)]
+        hi = [int(min((nx, ny, nz)[a], math.ceil(p[a] + r + 1))) for a in range(3)]
+        if lo[0] >= hi[0] or lo[1] >= hi[1] or lo[2] >= hi[2]:
+            continue
+        Z, Y, X = torch.meshgrid(kk[lo[2]:hi[2]], jj[lo[1]:hi[1]], ii[lo[0]:hi[0]], indexing="ij")
+        hole = (X - p[0]) ** 2 + (Y - p[1]) ** 2 + (Z - p[2]) ** 2 <= r * r
+        vol[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]].masked_fill_(hole, 0.0)
+    if blur_sigma > 0:
+        rad = int(4.0 * blur_sigma + 0.5)
+        t = np.arange(-rad, rad + 1, dtype=np.float64)
+        w = np.exp(-0.5 * (t / blur_sigma) ** 2)
+        w /= w.sum()
+        for axis in range(3):
+            out = torch.empty_like(vol)
+            for k0 in range(0, nz, 64):  # FP64 sums, a z-slab at a time
+                k1 = min(nz, k0 + 64)
+                if axis == 0:
+                    src = vol[max(0, k0 - rad):min(nz, k1 + rad)].double()
+                    off = k0 - max(0, k0 - rad)
+                else:
+                    src = vol[k0:k1].double()
+                    off = 0
+                dim = 0 if axis == 0 else axis
+                n_ax = src.shape[dim]
+                m = k1 - k0 if axis == 0 else n_ax
+                acc = w[rad] * src.narrow(dim, off, m)
+                for s in range(1, rad + 1):
+                    # x_{i+s} + x_{i-s}, zero outside the grid
+                    up = torch.zeros_like(acc)
+                    dn = torch.zeros_like(acc)
+                    a0, a1 = max(0, off + s), min(n_ax, off + m + s)
+                    if a1 > a0:
+                        up.narrow(dim, a0 - off - s, a1 - a0).copy_(src.narrow(dim, a0, a1 - a0))
+                    b0, b1 = max(0, off - s), min(n_ax, off + m - s)
+                    if b1 > b0:
+                        dn.narrow(dim, b0 - off + s, b1 - b0).copy_(src.narrow(dim, b0, b1 - b0))
+                    acc += w[rad + s] * (up + dn)
+                out[k0:k1] = acc.float()
+                del src, acc
+            vol = out
+    return vol
 
 
 def phantom(name: str, g: dict | None = None, **overrides) -> np.ndarray:
@@ -280,24 +349,38 @@ def add_noise(b_clean, spec: dict, seed: int) -> tuple[np.ndarray, dict]:
 def add_noise_torch(b_clean, spec: dict, seed: int):
     """``add_noise`` for a torch tensor, drawn on the tensor's device (for
     projections too large to round-trip through host memory).  Same model,
-    different random stream (torch's generator)."""
+    different random stream (torch's generator).  Tensors of more than 2^28
+    elements are drawn in blocks of whole leading-axis slices (angles), block
+    by block from one generator, so that no single draw exceeds 2^28
+    elements."""
     import torch
 
     gen = torch.Generator(device=b_clean.device).manual_seed(seed + 1000)
     info = {}
-    if spec["kind"] == "gaussian":
-        sig = spec["rel_sigma"] * float(b_clean.abs().max())
-        out = b_clean + sig * torch.randn(b_clean.shape, generator=gen, device=b_clean.device)
-    elif spec["kind"] == "poisson":
-        i0, L = float(spec["i0"]), float(spec.get("length_unit_mm", 1.0))
-        counts = torch.poisson(i0 * torch.exp(-b_clean.double() / L), generator=gen)
-        info["clamped_fraction"] = float((counts < 1.0).double().mean())
-        out = L * torch.log(i0 / counts.clamp_(min=1.0))
-    elif spec["kind"] == "none":
-        out = b_clean
-    else:
+    if spec["kind"] == "none":
+        return b_clean.float().contiguous(), info
+    if spec["kind"] not in ("gaussian", "poisson"):
         raise ValueError(spec["kind"])
-    return out.float().contiguous(), info
+    out = torch.empty(b_clean.shape, dtype=torch.float32, device=b_clean.device)
+    per = max(1, b_clean[0].numel()) if b_clean.dim() > 0 else 1
+    step = max(1, (1 << 28) // per) if b_clean.dim() > 0 else 1
+    n_lead = b_clean.shape[0] if b_clean.dim() > 0 else 1
+    sig = spec.get("rel_sigma", 0.0) * float(b_clean.abs().max()) if spec["kind"] == "gaussian" else 0.0
+    clamped = 0
+    for a0 in range(0, n_lead, step):
+        blk = b_clean[a0:a0 + step] if b_clean.dim() > 0 else b_clean
+        dst = out[a0:a0 + step] if b_clean.dim() > 0 else out
+        if spec["kind"] == "gaussian":
+            dst.copy_(blk + sig * torch.randn(blk.shape, generator=gen, device=blk.device))
+        else:
+            i0, L = float(spec["i0"]), float(spec.get("length_unit_mm", 1.0))
+            counts = torch.poisson(i0 * torch.exp(-blk.double() / L), generator=gen)
+            clamped += int((counts < 1.0).sum())
+            dst.copy_(L * torch.log(i0 / counts.clamp_(min=1.0)))
+            del counts
+    if spec["kind"] == "poisson":
+        info["clamped_fraction"] = clamped / max(1, b_clean.numel())
+    return out, info
 
 
 def random_volume(shape, seed: int, lo: float = 0.0, hi: float = 1.0) -> np.ndarray:
