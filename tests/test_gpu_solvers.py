@@ -67,6 +67,8 @@ CASES = [
     ("torso40", "lsqr", 30, 10.0),
     ("torso40", "lsmr", 30, 10.0),
     ("torso40", "cgls", 30, 10.0),
+    # The torso workload's own iteration count (50) at its lambda.
+    ("torso40", "lsqr", 50, 10.0),
 ]
 
 
@@ -95,11 +97,12 @@ def test_solver_matches_oracle(kct, name, solver, n_iter, lam):
     np.testing.assert_allclose(h[:5, 2], rh["beta"][:5], rtol=1e-3)
 
 
-def test_hybrid_lsqr_matches_oracle_and_damped_lsqr(kct):
+@pytest.mark.parametrize("k", [25, 50])
+def test_hybrid_lsqr_matches_oracle_and_damped_lsqr(kct, k):
     og, kg, b = _problem("torso40")
     plan = kct.Plan(kg)
     bt = torch.from_numpy(b).to(DEV)
-    lam, k = 10.0, 25
+    lam = 10.0
     xh, hh = plan.solve(bt, "hybrid_lsqr", k, lam)
     xd, hd = plan.solve(bt, "lsqr", k, lam)
     torch.cuda.synchronize()

@@ -58,6 +58,32 @@ def test_irn_tv_matches_oracle(kct, outer, inner, lam):
     assert float(S.tv(x.cpu().numpy().astype(np.float64))) > 0
 
 
+# The micro-CT workload's TV setting (lambda 10, eps 1e-3) in its storage: the
+# projection-side vectors in FP16, x and the Krylov scalars as always.  A
+# shortened schedule (3 outer x 10 inner) on the 32^3 crop.  The FP32 path is
+# held to the solver gate; the FP16 bound is empirical (measured on this
+# crop, see the DESIGN notes on 16-bit storage), relative L2 against the FP64
+# oracle.
+IRN_MUCT_BOUND = {torch.float32: 1e-5, torch.float16: 3e-3}
+
+
+@pytest.mark.parametrize("dt", [torch.float32, torch.float16])
+def test_irn_tv_muct_setting(kct, dt):
+    gd, og, xt, b = _muct_crop()
+    outer, inner, lam, eps = 3, 10, 10.0, 1e-3
+    print(f"[irn-tv muct] {outer}x{inner} lam={lam} {dt}", flush=True)
+    plan = kct.Plan(kct.Geometry.from_dict(gd))
+    x, h = plan.solve(torch.from_numpy(b).to(DEV), "irn_tv_cgls", 0, lam, vec_dtype=dt, tv_outer=outer,
+                      tv_inner=inner, tv_eps=eps)
+    torch.cuda.synchronize()
+    ref, _ = S.irn_tv_cgls(lambda v: oracle.forward(og, v), lambda y: oracle.adjoint(og, y),
+                           b.astype(np.float64), og.vol_shape, outer, inner, lam, eps)
+    e = _rel(x.cpu().numpy(), ref)
+    print(f"[irn-tv muct] {dt}: rel L2 vs FP64 oracle {e:.2e}", flush=True)
+    assert torch.all(torch.isfinite(x)) and torch.all(h[:, 3] == 0)
+    assert e <= IRN_MUCT_BOUND[dt]
+
+
 def test_irn_tv_outer_restart_reduces_tv(kct):
     """More outer reweighting steps lower the TV of the reconstruction relative
     to the same number of plain CGLS steps with the L = I penalty."""
