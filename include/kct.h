@@ -176,6 +176,26 @@ kct_status kct_forward(kct_plan *plan, const void *d_vol, int32_t vol_dtype, voi
                        int32_t proj_dtype, void *stream);
 
 /*
+ * Forward projection that allocates nothing, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments and result as kct_forward
+ * (bitwise: the same kernels), but the padded volume copies live in a device
+ * array of KCT_NOALLOC_SCRATCH_BYTES that the library holds, on each GPU it
+ * runs on, until the process ends; kct_plan_reserve is not needed.  The
+ * copies take 2 (nx+2)(ny+2)(nz+2) elements of FP32 (for volumes the plan
+ * widens, see KCT_FWD_PAD_F32) or of the volume's type: up to 254^3 voxels
+ * in FP32.  Larger volumes: KCT_E_BUDGET, nothing enqueued.  KCT_E_DEVICE if
+ * the array's device address could not be resolved when the plan was
+ * created.  Every call on one GPU shares that GPU's array, which keeps the
+ * last call's contents (each call rewrites all of it before reading it):
+ * calls that overlap in time on one GPU, from any stream, thread or plan,
+ * race, and their projections are undefined.  Enqueued on `stream`.
+ */
+#define KCT_NOALLOC_SCRATCH_BYTES (128u << 20)
+kct_status kct_forward_noalloc(kct_plan *plan, const void *d_vol, int32_t vol_dtype, void *d_proj,
+                               int32_t proj_dtype, void *stream);
+
+/*
  * Back projection with the exact transpose of kct_forward (paper Sec. 2.1.4
  * and Sec. 4: a mismatched back projector degrades the Krylov methods):
  * d_vol = A^T d_proj.  Voxel-driven gather; FP32 accumulation.  Layouts as in

@@ -194,6 +194,18 @@ class Plan:
                                                _stream_ptr(stream)), "kct_forward")
         return out
 
+    def forward_noalloc(self, vol: torch.Tensor, out: torch.Tensor, stream=None):
+        """A vol into ``out`` through kct_forward_noalloc: the library allocates
+        nothing (its padded copies live in a static device array of
+        KCT_NOALLOC_SCRATCH_BYTES shared by every call on the GPU)."""
+        self._check(vol, self.geom.vol_shape, "volume")
+        self._check(out, self.geom.proj_shape, "projections")
+        with torch.cuda.device(self.device):
+            _lib.check(_lib.load().kct_forward_noalloc(self._h, ctypes.c_void_p(vol.data_ptr()), dtype_code(vol.dtype),
+                                                       ctypes.c_void_p(out.data_ptr()), dtype_code(out.dtype),
+                                                       _stream_ptr(stream)), "kct_forward_noalloc")
+        return out
+
     def backproject(self, proj: torch.Tensor, out: torch.Tensor | None = None, out_dtype=None, stream=None):
         """A^T proj: matched back projection, (nz, ny, nx)."""
         self._check(proj, self.geom.proj_shape, "projections")

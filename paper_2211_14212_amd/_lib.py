@@ -33,7 +33,7 @@ KCT_LAMBDA_FIXED, KCT_LAMBDA_GCV, KCT_LAMBDA_DP = 0, 1, 2
 
 EXPORTED = [
     "kct_plan_create", "kct_plan_destroy", "kct_plan_reserve", "kct_plan_check", "kct_plan_device_bytes",
-    "kct_forward", "kct_backproject",
+    "kct_forward", "kct_forward_noalloc", "kct_backproject",
     "kct_backproject_interp",
     "kct_solve_workspace_bytes", "kct_solve", "kct_state_create", "kct_state_step", "kct_state_progress",
     "kct_state_resume",
@@ -92,6 +92,7 @@ def load(path: str = LIB_PATH):
         "kct_plan_check": ([vp, vp], st),
         "kct_plan_device_bytes": ([vp, P(sz)], st),
         "kct_forward": ([vp, vp, i32, vp, i32, vp], st),
+        "kct_forward_noalloc": ([vp, vp, i32, vp, i32, vp], st),
         "kct_backproject": ([vp, vp, i32, vp, i32, vp], st),
         "kct_backproject_interp": ([vp, vp, i32, vp, i32, vp], st),
         "kct_solve_workspace_bytes": ([vp, P(KctSolveParams), P(sz)], st),

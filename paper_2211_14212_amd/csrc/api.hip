@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 namespace kct {
@@ -31,6 +32,38 @@ struct DeviceGuard {
 };
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// Scratch of kct_forward_noalloc: the forward projector's padded volume
+// copies in a device array the library owns (each GPU the library runs on
+// holds its own copy of it until the process ends).  In host code the array's
+// name is not a device address: the address of each GPU's copy is resolved
+// once per device, at plan creation with that device current, and kept in
+// g_scratch; only those addresses are passed to kernels.
+constexpr size_t NOALLOC_SCRATCH_BYTES = KCT_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[SCRATCH_DEVICES] = {};
+bool g_scratch_tried[SCRATCH_DEVICES] = {};
+
+// With device `dev` current.  A failure leaves the address unset, which
+// kct_forward_noalloc then reports; the plan itself does not depend on it.
+void resolve_scratch(int dev)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (dev < 0 || dev >= SCRATCH_DEVICES || g_scratch_tried[dev]) return;
+    g_scratch_tried[dev] = true;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e == hipSuccess && ptr) g_scratch[dev] = ptr;
+    else (void)hipGetLastError(); // do not leave the failure for the caller's next HIP call
+}
+
+void *scratch_address(int dev)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return (dev >= 0 && dev < SCRATCH_DEVICES) ? g_scratch[dev] : nullptr;
+}
 } // namespace
 
 void set_error(const std::string &msg) { g_last_error = msg; }
@@ -207,6 +240,7 @@ kct_status kct_plan_create(const kct_geometry *geom, int device, kct_plan **out)
         delete p;
         return fail(KCT_E_DEVICE, "hipSetDevice failed");
     }
+    resolve_scratch(device);
     // 1/v per detector row.  The central row of an odd detector (v = 0) gets
     // 1e300 instead of infinity: z/v then maps a voxel with z0 <= 0 < z1 to an
     // interval covering every ray parameter in (0, 1) and excludes the others,
@@ -332,6 +366,30 @@ kct_status kct_forward(kct_plan *p, const void *d_vol, int32_t vol_dtype, void *
     if (s != KCT_OK) return s;
     Epilogue ep;
     return launch_forward(*p, p->d_pad, pdt, d_proj, proj_dtype, ep, st);
+}
+
+kct_status kct_forward_noalloc(kct_plan *p, const void *d_vol, int32_t vol_dtype, void *d_proj, int32_t proj_dtype,
+                               void *stream)
+{
+    g_last_error.clear();
+    if (!p || !d_vol || !d_proj) return fail(KCT_E_INVALID_ARG, "NULL argument");
+    if (!dtype_ok(vol_dtype) || !dtype_ok(proj_dtype)) return fail(KCT_E_DTYPE, "unknown storage type");
+    const int pdt = fwd_pad_dtype(*p, vol_dtype);
+    const size_t need = size_t(2 * p->pad.vox) * dtype_size(pdt);
+    if (need > NOALLOC_SCRATCH_BYTES)
+        return fail(KCT_E_BUDGET, "the padded volume copies (" + std::to_string(need) + " bytes) exceed the " +
+                                      std::to_string(NOALLOC_SCRATCH_BYTES) + "-byte static scratch of "
+                                      "kct_forward_noalloc: use kct_plan_reserve and kct_forward");
+    void *pad = scratch_address(p->device);
+    if (!pad) return fail(KCT_E_DEVICE, "the static scratch's device address could not be resolved");
+    DeviceGuard dg(p->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // The pad kernel writes every element of both copies, border included, so
+    // nothing left by an earlier call is read.
+    kct_status s = launch_pad_volume_as(*p, d_vol, vol_dtype, pdt, pad, st);
+    if (s != KCT_OK) return s;
+    Epilogue ep;
+    return launch_forward(*p, pad, pdt, d_proj, proj_dtype, ep, st);
 }
 
 kct_status kct_backproject(kct_plan *p, const void *d_proj, int32_t proj_dtype, void *d_vol, int32_t vol_dtype,
