@@ -445,8 +445,8 @@ def serving_leg(args, torch):
     log("[bench] serving stream")
     torch.cuda.empty_cache()
     reqs = serve.make_requests(args.serve_requests, 2.0, seed=5, size_scale=args.serve_scale)
-    batched = serve.summarize(serve.Server(200e9, keep_results=False).run(reqs))
-    serial = serve.summarize(serve.serve_serial(reqs, keep_results=False))
+    batched = serve.summarize(serve.Server(200e9, keep_results=False).run(reqs), rate=2.0)
+    serial = serve.summarize(serve.serve_serial(reqs, keep_results=False), rate=2.0)
     out = {"requests": args.serve_requests, "rate_per_s": 2.0, "size_scale": args.serve_scale,
            "batched": {k: round(v, 4) for k, v in batched.items()},
            "serial": {k: round(v, 4) for k, v in serial.items()}}
@@ -543,8 +543,10 @@ def main():
     ap.add_argument("--vec-dtype", default=None, choices=sorted(DTYPES),
                     help="storage of the projector-facing Krylov vectors (default: f16 for the micro-CT "
                          "workload, else f32)")
-    ap.add_argument("--serve-requests", type=int, default=16)
-    ap.add_argument("--serve-scale", type=float, default=0.25)
+    ap.add_argument("--serve-requests", type=int, default=32)
+    ap.add_argument("--serve-scale", type=float, default=0.75,
+                    help="volume side, detector side and angle count of the request stream, relative to the "
+                         "workload's (0.75: offered load above one at 2 requests/s)")
     ap.add_argument("--precision", action="store_true",
                     help="the 16-bit storage report instead of the step benchmark: LSQR and hybrid LSQR "
                          "(lambda 10, 50 iterations) with FP32, BF16 and FP16 vectors, each compared with the "

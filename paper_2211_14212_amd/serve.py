@@ -5,9 +5,14 @@ count) arrive over time.  The server admits them in arrival order while the
 HBM they need (plan tables, workspace, b, x, history) fits a byte budget,
 gives each admitted request its own HIP stream and device-resident Krylov
 state (kct_state), and advances all active requests one iteration at a time,
-so kernels of different requests overlap on the GPU.  A request leaves when
-its last iteration has run on the device; its memory is freed and queued
-requests are admitted in its place.  Each request's result is bitwise the
+so kernels of different requests overlap on the GPU.  Each request keeps up
+to ``depth`` iterations enqueued ahead of the device (2 by default), so its
+stream never waits for the host between iterations.  Plans (the per-angle
+tables, whose build waits for the device) are made by a worker thread as
+requests arrive, off the serving loop.  A request leaves when its last
+iteration has run on the device; its memory is freed and queued requests are
+admitted in its place.  A request that needs more memory than the whole
+budget is rejected on arrival.  Each request's result is bitwise the
 same as a solo kct_solve of it (deterministic kernels, private buffers).
 Admission is first-come first-served by default; ``policy="sjf"`` admits the
 queued request with the least work first (ray-iterations, the cost of its
@@ -62,6 +67,7 @@ class Result:
     x: torch.Tensor | None
     history: torch.Tensor | None
     cancelled: bool = False
+    rejected: bool = False   # needs more memory than the whole budget
 
     @property
     def latency(self) -> float:
@@ -72,8 +78,13 @@ class _Active:
     def __init__(self, req: Request, plan: Plan, state, stream, nbytes: int, admitted: float):
         self.req, self.plan, self.state, self.stream = req, plan, state, stream
         self.nbytes, self.admitted = nbytes, admitted
-        self.event = None
+        self.events: deque = deque()  # one per enqueued step not yet seen complete
         self.enqueued = 0
+
+    def drain(self) -> None:
+        """Forget the steps the device has finished."""
+        while self.events and self.events[0].query():
+            self.events.popleft()
 
 
 def request_work(req: Request) -> int:
@@ -91,10 +102,13 @@ def request_bytes(plan: Plan, req: Request) -> int:
 
 class Server:
     def __init__(self, budget_bytes: float = 200e9, device: int = 0, max_active: int = 16,
-                 keep_results: bool = True, verbose: bool = False, policy: str = "fifo"):
+                 keep_results: bool = True, verbose: bool = False, policy: str = "fifo", depth: int = 2):
         if policy not in ("fifo", "sjf"):
             raise ValueError(policy)
+        if depth < 1:
+            raise ValueError("depth must be at least 1")
         self.policy = policy
+        self.depth = depth
         self.budget = int(budget_bytes)
         self.device = torch.device("cuda", device)
         self.max_active = max_active
@@ -113,69 +127,99 @@ class Server:
         ``cancel_after`` maps a request id to an iteration count: the request
         is cancelled once that many of its iterations are enqueued (a
         deterministic trigger for ``cancel``)."""
+        from concurrent.futures import ThreadPoolExecutor
+
         cancel_after = dict(cancel_after or {})
         pending = deque(sorted(requests, key=lambda r: r.arrival))
         queue: deque[Request] = deque()
+        plans: dict = {}  # request id -> Future of its Plan, made by the worker thread
         active: list[_Active] = []
         used = 0
         results: dict[int, Result] = {}
+        dev = self.device.index
+
+        def make_plan(geom):
+            with torch.cuda.device(dev):
+                return Plan(geom, dev)
+
         t0 = time.perf_counter()
-        with torch.cuda.device(self.device):
+        with torch.cuda.device(self.device), ThreadPoolExecutor(max_workers=1) as worker:
             while pending or queue or active:
                 now = time.perf_counter() - t0
                 while pending and pending[0].arrival <= now:
-                    queue.append(pending.popleft())
+                    req = pending.popleft()
+                    queue.append(req)
+                    plans[req.id] = worker.submit(make_plan, req.geom)
                 # Cancelled requests still waiting leave at once.
                 if any(q.id in self._cancel for q in queue):
                     keep: deque[Request] = deque()
                     for req in queue:
                         if req.id in self._cancel:
                             results[req.id] = Result(req.id, req.arrival, now, now, None, None, cancelled=True)
+                            plans.pop(req.id).result().close()
                             self.log.append(("cancel", req.id, now, used))
                         else:
                             keep.append(req)
                     queue = keep
                 # Admission while the next request fits the budget: the head
-                # of the queue (FIFO) or the least work (SJF, ties by arrival).
+                # of the queue (FIFO) or the least work (SJF, ties by arrival),
+                # once its plan is ready.
                 while queue and len(active) < self.max_active:
                     i = 0 if self.policy == "fifo" else min(range(len(queue)), key=lambda k: request_work(queue[k]))
                     req = queue[i]
-                    plan = Plan(req.geom, self.device.index)
+                    if not plans[req.id].done():
+                        break
+                    plan = plans[req.id].result()
                     need = request_bytes(plan, req)
-                    if used + need > self.budget and active:
+                    if need > self.budget:
+                        del queue[i]
+                        plans.pop(req.id)
                         plan.close()
+                        t = time.perf_counter() - t0
+                        results[req.id] = Result(req.id, req.arrival, t, t, None, None, rejected=True)
+                        self.log.append(("reject", req.id, t, used))
+                        continue
+                    if used + need > self.budget:
                         break
                     del queue[i]
+                    plans.pop(req.id)
                     stream = torch.cuda.Stream(device=self.device)
                     state = plan.state(req.b, req.solver, req.n_iter, req.lam, req.vec_dtype, stream=stream)
                     used += need
                     a = _Active(req, plan, state, stream, need, time.perf_counter() - t0)
                     active.append(a)
                     self.log.append(("admit", req.id, a.admitted, used))
-                # Advance every active request whose previous step has finished.
+                # Keep up to `depth` iterations of every active request enqueued.
                 progressed = False
                 for a in active:
+                    a.drain()
                     if cancel_after.get(a.req.id, -1) == a.enqueued:
                         self._cancel.add(a.req.id)
                     if a.req.id in self._cancel:
                         continue
-                    if a.enqueued < a.req.n_iter and (a.event is None or a.event.query()):
+                    while 0 <= a.enqueued < a.req.n_iter and len(a.events) < self.depth:
                         a.state.step(1)
                         a.enqueued += 1
-                        a.event = torch.cuda.Event()
-                        a.event.record(a.stream)
+                        ev = torch.cuda.Event()
+                        ev.record(a.stream)
+                        a.events.append(ev)
                         progressed = True
-                    elif a.enqueued == 0 and a.req.n_iter == 0:
+                        if cancel_after.get(a.req.id, -1) == a.enqueued:
+                            self._cancel.add(a.req.id)
+                            break
+                    if a.enqueued == 0 and a.req.n_iter == 0:
                         a.state.step(0)
-                        a.event = torch.cuda.Event()
-                        a.event.record(a.stream)
+                        ev = torch.cuda.Event()
+                        ev.record(a.stream)
+                        a.events.append(ev)
                         a.enqueued = -1
+                        progressed = True
                 # Retire requests whose last iteration has completed.
                 still = []
                 for a in active:
                     cancelled = a.req.id in self._cancel
                     done_enq = a.enqueued == a.req.n_iter or a.enqueued == -1 or cancelled
-                    if done_enq and (a.event is None or a.event.query()):
+                    if done_enq and not a.events:
                         fin = time.perf_counter() - t0
                         keep = self.keep_results and not cancelled
                         x = a.state.x if keep else None
@@ -196,7 +240,9 @@ class Server:
                     if not active and not queue and pending:
                         time.sleep(max(0.0, min(0.01, pending[0].arrival - (time.perf_counter() - t0))))
                     else:
-                        time.sleep(0.0002)
+                        time.sleep(0.0001)
+            for f in plans.values():  # plans of requests that never ran (cancelled while queued)
+                f.result().close()
         return [results[r.id] for r in sorted(requests, key=lambda r: r.id)]
 
 
@@ -234,24 +280,31 @@ def percentile(values, q):
     return v[k - 1]
 
 
-def summarize(results: list[Result]) -> dict:
-    results = [r for r in results if not r.cancelled]
+def summarize(results: list[Result], rate: float | None = None) -> dict:
+    """Latency percentiles and throughput of the served requests.  With the
+    arrival ``rate``, also the offered load rho = rate x mean service time,
+    the service time being admission to completion (for the serial path, a
+    request's solve alone on the GPU)."""
+    results = [r for r in results if not r.cancelled and not r.rejected]
     lat = [r.latency for r in results]
     makespan = max(r.finished for r in results) - min(r.arrival for r in results)
-    return {"n": len(results), "p50_s": percentile(lat, 50), "p99_s": percentile(lat, 99),
-            "mean_s": float(np.mean(lat)), "throughput_req_per_s": len(results) / makespan,
-            "makespan_s": makespan}
+    out = {"n": len(results), "p50_s": percentile(lat, 50), "p99_s": percentile(lat, 99),
+           "mean_s": float(np.mean(lat)), "throughput_req_per_s": len(results) / makespan,
+           "makespan_s": makespan}
+    if rate is not None:
+        out["offered_load_rho"] = rate * float(np.mean([r.finished - r.admitted for r in results]))
+    return out
 
 
-def make_requests(n=64, rate=2.0, seed=5, size_scale=1.0, device=0, det_scale=None, angle_scale=None):
-    """The seeded request stream of synth.serve_stream, with projections of a
-    random ellipsoid phantom (GPU forward projection, Poisson noise I0 = 1e5)."""
+def stream_specs(n=64, rate=2.0, seed=5, size_scale=1.0, det_scale=None, angle_scale=None):
+    """The seeded request stream of synth.serve_stream, shrunk by the scales:
+    per request a dict with its id, arrival, geometry dict, solver, iteration
+    count and the seed and ellipsoid count of its phantom."""
     import synth
 
-    dev = torch.device("cuda", device)
     det_scale = size_scale if det_scale is None else det_scale
     angle_scale = size_scale if angle_scale is None else angle_scale
-    reqs = []
+    out = []
     for r in synth.serve_stream(n, rate, seed):
         g = dict(r["geom"])
         n_vox = max(8, int(round(g["nx"] * size_scale)))
@@ -259,13 +312,33 @@ def make_requests(n=64, rate=2.0, seed=5, size_scale=1.0, device=0, det_scale=No
         na = max(4, int(round(g["n_angles"] * angle_scale)))
         pitch = 1.1 * n_vox * 0.5 * (g["dsd"] / g["dso"]) / side
         g.update(nx=n_vox, ny=n_vox, nz=n_vox, nu=side, nv=side, du=pitch, dv=pitch, n_angles=na)
-        gd = synth.geometry(g)
-        geom = Geometry.from_dict(gd)
-        xt = synth.ellipsoid_phantom(gd, r["n_ellipsoids"], (2.0, 12.0 * n_vox / 128), (0.01, 0.05), r["seed"])
+        out.append(dict(r, geom=synth.geometry(g)))
+    return out
+
+
+def request_phantom(spec) -> np.ndarray:
+    """The random ellipsoid phantom of one request (attenuation 0.01-0.05 per
+    mm, i.e. 0.1-0.5 per cm)."""
+    import synth
+
+    gd = spec["geom"]
+    return synth.ellipsoid_phantom(gd, spec["n_ellipsoids"], (2.0, 12.0 * gd["nx"] / 128), (0.01, 0.05),
+                                   spec["seed"])
+
+
+def make_requests(n=64, rate=2.0, seed=5, size_scale=1.0, device=0, det_scale=None, angle_scale=None):
+    """The seeded request stream (``stream_specs``), with projections of each
+    request's phantom made on the GPU (forward projection, Poisson noise at
+    I0 = 1e5)."""
+    import synth
+
+    dev = torch.device("cuda", device)
+    reqs = []
+    for r in stream_specs(n, rate, seed, size_scale, det_scale, angle_scale):
+        geom = Geometry.from_dict(r["geom"])
         plan = Plan(geom, device)
-        # Attenuation 0.01-0.05 per mm (0.1-0.5 per cm); Poisson counts at I0 = 1e5.
-        b, _ = synth.add_noise_torch(plan.forward(torch.from_numpy(xt).to(dev)), dict(kind="poisson", i0=1.0e5),
-                                     r["seed"])
+        b, _ = synth.add_noise_torch(plan.forward(torch.from_numpy(request_phantom(r)).to(dev)),
+                                     dict(kind="poisson", i0=1.0e5), r["seed"])
         plan.close()
         reqs.append(Request(r["id"], r["arrival"], geom, b, r["solver"], r["n_iter"]))
         if len(reqs) % 8 == 0:

@@ -70,6 +70,26 @@ def test_budget_respected(stream):
     assert len([a for a in srv.log if a[0] == "admit"]) == len(reqs)
 
 
+def test_oversized_request_rejected(stream):
+    """A request that needs more than the whole budget is rejected (it could
+    never be admitted); the others are served as usual."""
+    serve, reqs = stream
+    plans = [serve.Plan(r.geom) for r in reqs]
+    sizes = [serve.request_bytes(p, r) for p, r in zip(plans, reqs)]
+    for p in plans:
+        p.close()
+    budget = 1.01 * sorted(sizes)[len(sizes) // 2]
+    big = {r.id for r, n in zip(reqs, sizes) if n > budget}
+    assert big and len(big) < len(reqs)
+    srv = serve.Server(budget_bytes=budget, max_active=8, keep_results=False)
+    res = srv.run(reqs)
+    for r in res:
+        assert r.rejected == (r.id in big) and not r.cancelled, r.id
+    assert {e[1] for e in srv.log if e[0] == "reject"} == big
+    assert max(u for (_, _, _, u) in srv.log) <= budget
+    assert serve.summarize(res)["n"] == len(reqs) - len(big)
+
+
 def test_cancel_leaves_others_bitwise(stream):
     serve, reqs = stream
     victim, early = reqs[1].id, reqs[-1].id
@@ -93,37 +113,94 @@ def test_cancel_leaves_others_bitwise(stream):
     assert serve.summarize(res)["n"] == len(reqs) - 2
 
 
-def test_small_request_matches_oracle(stream):
-    """The smallest request of the mix against the FP64 oracle.  Its Krylov
-    run is long for its size (20-50 iterations on a 32^3 noisy problem), the
-    regime where rounding is amplified, so the gate is 1e-5 or 4x the
-    intrinsic sensitivity, whichever is larger: the oracle re-run with every
-    matvec output perturbed by 5e-7 relative noise (the size of the GPU's FP32
-    accumulation error) and rounded to FP32."""
-    serve, reqs = stream
-    req = min(reqs, key=lambda r: r.geom.n_voxels * len(r.geom.angles))
-    srv = serve.Server(budget_bytes=50e9)
-    (res,) = srv.run([req])
-    g = oracle.Geometry.from_dict(dict(nx=req.geom.nx, ny=req.geom.ny, nz=req.geom.nz, vx=req.geom.vx,
-                                       vy=req.geom.vy, vz=req.geom.vz, nu=req.geom.nu, nv=req.geom.nv,
-                                       du=req.geom.du, dv=req.geom.dv, dso=req.geom.dso, dsd=req.geom.dsd,
-                                       angles=req.geom.angles))
-    b = req.b.cpu().numpy().astype(np.float64)
-    fn = getattr(S, req.solver)
-    A, AT = (lambda v: oracle.forward(g, v)), (lambda y: oracle.adjoint(g, y))
-    ref, _ = fn(A, AT, b, req.n_iter, req.lam)
+def _host_requests(serve, reqs, ids):
+    """Requests ``ids`` of the mix with their projections made on the host by
+    the oracle (the request's phantom, FP64 forward projection, seeded Poisson
+    counts at I0 = 1e5, rounded to FP32), so that no oracle input comes from
+    the GPU; the other requests keep their GPU-made projections."""
+    import dataclasses
+
+    import synth
+
+    specs = {sp["id"]: sp for sp in serve.stream_specs(n=10, rate=20.0, seed=5, size_scale=0.125,
+                                                           angle_scale=0.1)}
+    host, out = {}, []
+    for req in reqs:
+        if req.id in ids:
+            sp = specs[req.id]
+            og = oracle.Geometry.from_dict(sp["geom"])
+            b, _ = synth.add_noise(oracle.forward(og, serve.request_phantom(sp)), dict(kind="poisson", i0=1.0e5),
+                                   sp["seed"])
+            host[req.id] = (og, b.astype(np.float64))
+            req = dataclasses.replace(req, b=torch.from_numpy(b).to(req.b.device))
+        out.append(req)
+    return out, host
+
+
+def _oracle_and_sensitivity(og, b, solver, k):
+    """The oracle's iterate and the intrinsic sensitivity of the run: the
+    relative change when every matvec output is rounded to FP32 (the
+    sensitivity the parity gate is judged by), and when it is also perturbed
+    by 5e-7 relative Gaussian noise (about the size of a GPU ray or voxel sum's
+    FP32 accumulation error)."""
+    fn = getattr(S, solver)
+    A, AT = (lambda v: oracle.forward(og, v)), (lambda y: oracle.adjoint(og, y))
+    ref, _ = fn(A, AT, b, k)
     rng = np.random.default_rng(0)
 
-    def perturbed(f):
+    def to32(f, noise):
         def g(z):
             y = f(z)
-            return (y * (1 + 5e-7 * rng.standard_normal(y.shape))).astype(np.float32).astype(np.float64)
+            if noise:
+                y = y * (1 + 5e-7 * rng.standard_normal(y.shape))
+            return y.astype(np.float32).astype(np.float64)
         return g
 
-    alt, _ = fn(perturbed(A), perturbed(AT), b, req.n_iter, req.lam)
-    sens = np.linalg.norm(alt - ref) / np.linalg.norm(ref)
-    got = res.x.cpu().numpy()
-    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
-    print(f"[serve oracle] {req.solver} k={req.n_iter} {req.geom.vol_shape}: err {err:.2e}, sensitivity {sens:.2e}",
-          flush=True)
-    assert err <= max(1e-5, 4 * sens)
+    def sens(noise):
+        alt, _ = fn(to32(A, noise), to32(AT, noise), b, k)
+        return float(np.linalg.norm(alt - ref) / np.linalg.norm(ref))
+
+    return ref, sens(False), sens(True)
+
+
+# Requests of the seeded mix whose runs are insensitive to FP32 rounding (the
+# oracle's relative change with every matvec output rounded to FP32 is about
+# 1e-7 for each): held to the flat 1e-5 gate.
+FLAT_IDS = (3, 4, 6, 9)
+
+
+def test_mix_requests_match_oracle_flat(stream):
+    """Low-sensitivity requests, served in the mix, against the FP64 oracle at
+    a flat relative L2 of 1e-5."""
+    serve, reqs = stream
+    mixed, host = _host_requests(serve, reqs, FLAT_IDS)
+    res = {r.id: r for r in serve.Server(budget_bytes=50e9, max_active=6).run(mixed)}
+    for rid in FLAT_IDS:
+        req = next(r for r in mixed if r.id == rid)
+        og, b = host[rid]
+        ref, s32, snoise = _oracle_and_sensitivity(og, b, req.solver, req.n_iter)
+        err = float(np.linalg.norm(res[rid].x.cpu().numpy() - ref) / np.linalg.norm(ref))
+        print(f"[serve oracle flat] request {rid} {req.solver}-{req.n_iter} {req.geom.vol_shape}: err {err:.2e}, "
+              f"sensitivity FP32 rounding {s32:.2e}, with 5e-7 noise {snoise:.2e}", flush=True)
+        assert s32 <= 1e-6, rid
+        assert err <= 1e-5, rid
+
+
+def test_small_request_matches_oracle(stream):
+    """The smallest request of the mix against the FP64 oracle.  Its run
+    (LSMR-25 on 32^3 with 18 angles) is sensitive to rounding: the oracle
+    moves by about 2e-6 when every matvec output is rounded to FP32, and by
+    about 1e-3 when the outputs also carry 5e-7 relative noise, the size of
+    the GPU's FP32 accumulation error.  The gate is therefore 1e-5 or 4x the
+    latter, whichever is larger; the flat 1e-5 gate is held on the
+    low-sensitivity requests above."""
+    serve, reqs = stream
+    req = min(reqs, key=lambda r: r.geom.n_voxels * len(r.geom.angles))
+    mixed, host = _host_requests(serve, [req], (req.id,))
+    (res,) = serve.Server(budget_bytes=50e9).run(mixed)
+    og, b = host[req.id]
+    ref, s32, snoise = _oracle_and_sensitivity(og, b, req.solver, req.n_iter)
+    err = float(np.linalg.norm(res.x.cpu().numpy() - ref) / np.linalg.norm(ref))
+    print(f"[serve oracle] request {req.id} {req.solver}-{req.n_iter} {req.geom.vol_shape}: err {err:.2e}, "
+          f"sensitivity FP32 rounding {s32:.2e}, with 5e-7 noise {snoise:.2e}", flush=True)
+    assert err <= max(1e-5, 4 * snoise)
