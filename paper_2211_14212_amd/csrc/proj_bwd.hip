@@ -425,6 +425,7 @@ __global__ __launch_bounds__(256) void k_backward_rays(const TP *__restrict__ pr
     const int chunks = int(gridDim.y), chunk = int(blockIdx.y);
     const int a_begin = int(int64_t(g.na) * chunk / chunks), a_end = int(int64_t(g.na) * (chunk + 1) / chunks);
     __shared__ float sums[BR_COPIES][BR_VOX];
+    __shared__ float junk_cell[1]; // sink of the walk's skipped segments (never read back)
     __shared__ int4 fps[BR_FP];
     __shared__ double red[4];
 
@@ -493,6 +494,7 @@ __global__ __launch_bounds__(256) void k_backward_rays(const TP *__restrict__ pr
                 const float yv = to_f32(proj[int64_t(aa) * g.nv * g.nu + pix]) * dlen[pix];
                 if (yv == 0.f) continue;
                 float *acc = sums[(aa - a_begin) % BR_COPIES];
+                float *junk = junk_cell;
 
                 // The ray from the source to the pixel centre, in the voxel
                 // frame (voxel (i,j,k) = [i,i+1) x [j,j+1) x [k,k+1)), clipped
@@ -544,23 +546,39 @@ __global__ __launch_bounds__(256) void k_backward_rays(const TP *__restrict__ pr
                 // Each step ends the current segment at the first crossing
                 // (or the exit) and advances exactly one axis, x before y
                 // before z on ties (a tie leaves a zero-length segment in a
-                // diagonal neighbour, which is skipped).  While t < tmax the
-                // walk stays inside the tile, so every written index is one
-                // of the tile's voxels; at most nx+ny+nz+3 steps.
+                // diagonal neighbour).  While t < tmax the walk stays inside
+                // the tile; at most nx+ny+nz+3 steps.  The sum of the next
+                // voxel is read before the current one is written (they are
+                // different voxels), so the read's latency overlaps a whole
+                // step.  Segments no longer than BR_MIN_LEN (ties, and the
+                // rounding-level step out of the tile at the exit) are
+                // written to a scratch cell instead, and a read index outside
+                // the tile is clamped into it (its value is then unused).
+                // Two segments per trip, so that each read has a register of
+                // its own and the loop carries no copy that would wait for it.
+#define KCT_BR_STEP(CUR, NEXT)                                                                             \
+    {                                                                                                      \
+        const double m1 = fmin(txc, tyc);                                                                  \
+        const double t1 = fmin(m1, tzc);                                                                   \
+        const bool xy = txc <= tyc, first = m1 <= tzc;                                                     \
+        float *dst = acc + off;                                                                            \
+        off += first ? (xy ? sx : sy) : sz;                                                                \
+        NEXT = acc[min(max(off, 0), BR_VOX - 1)];                                                          \
+        txc = fma(br_one_if(xy && first), dtx, txc);                                                       \
+        tyc = fma(br_one_if(!xy && first), dty, tyc);                                                      \
+        tzc = fma(br_one_if(!first), dtz, tzc);                                                            \
+        const double len = fmin(t1, tmax) - tc;                                                            \
+        if (!(len > BR_MIN_LEN)) dst = junk;                                                               \
+        *dst = fmaf(float(len), yv, CUR);                                                                  \
+        if (!(t1 < tmax)) break;                                                                           \
+        tc = t1;                                                                                           \
+    }
+                float ca = acc[min(max(off, 0), BR_VOX - 1)], cb;
                 for (;;) {
-                    const double m1 = fmin(txc, tyc);
-                    const double t1 = fmin(m1, tzc);
-                    const double tn = fmin(t1, tmax);
-                    const double len = tn - tc;
-                    if (len > BR_MIN_LEN) acc[off] = fmaf(float(len), yv, acc[off]);
-                    if (!(t1 < tmax)) break;
-                    const bool xy = txc <= tyc, first = m1 <= tzc;
-                    txc = fma(br_one_if(xy && first), dtx, txc);
-                    tyc = fma(br_one_if(!xy && first), dty, tyc);
-                    tzc = fma(br_one_if(!first), dtz, tzc);
-                    off += first ? (xy ? sx : sy) : sz;
-                    tc = t1;
+                    KCT_BR_STEP(ca, cb)
+                    KCT_BR_STEP(cb, ca)
                 }
+#undef KCT_BR_STEP
             }
             __syncthreads(); // this pass's sums are complete before its copies take the next angles
             a += m;
