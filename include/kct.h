@@ -109,7 +109,8 @@ typedef struct kct_plan kct_plan;
  * The plan also fixes the projectors' launch shapes from the geometry.  For
  * tuning, these environment variables, read here, override the choice
  * (values outside the listed sets are ignored):
- *   KCT_FWD_PREFETCH     0 or 1   forward gathers one segment ahead (1)
+ *   KCT_FWD_PREFETCH     0, 1, 2  segments the forward gathers ahead (2 for
+ *                                 volumes with 16-bit padded copies, else 1)
  *   KCT_FWD_LANES_U      16, 32, 64  pixels per wave row in the forward
  *                                 (32 when neighbouring rays are a voxel or
  *                                 more apart at the axis, else 16)

@@ -164,9 +164,18 @@ void choose_fwd_shape(Plan &p)
     // 4 GiB, the 16-bit copies' halved gather traffic wins (1500^3: 3.64
     // against 3.92 s).
     p.fwd_pad_f32 = 2 * p.pad.vox * int64_t(sizeof(float)) < int64_t(0xffffffffLL);
-    // Tuning override: KCT_FWD_PREFETCH=0 selects the forward loop without
-    // the one-step-ahead gather.
-    if (const char *e = std::getenv("KCT_FWD_PREFETCH")) p.fwd_prefetch = std::atoi(e) != 0;
+    // Gathers in flight: two segments ahead where the padded copies stay
+    // 16-bit (the volume is large and a fraction of the gathers go to HBM:
+    // 1500^3, 3.50 -> 3.33 s), else one (the FP32-copy volumes are L2- and
+    // MALL-resident and the deeper loop's extra selects cost more: 256^3,
+    // 17.4 against 18.3 ms).
+    p.fwd_prefetch = p.fwd_pad_f32 ? 1 : 2;
+    // Tuning override: KCT_FWD_PREFETCH selects how many segments ahead the
+    // forward loop gathers (0, 1 or 2).
+    if (const char *e = std::getenv("KCT_FWD_PREFETCH")) {
+        const int d = std::atoi(e);
+        if (d >= 0 && d <= 2) p.fwd_prefetch = d;
+    }
     // Tuning override: the forward wave's patch width in detector columns.
     if (const char *e = std::getenv("KCT_FWD_LANES_U")) {
         const int lu = std::atoi(e);

@@ -111,7 +111,7 @@ struct Plan {
     int bwd_asplit = 1;           // angle chunks of the back projector (small volumes: > 1)
     float *d_split = nullptr;     // partial volumes for plain kct_backproject calls (at plan creation)
     size_t split_bytes = 0;       // capacity of d_split
-    bool fwd_prefetch = true;     // forward projector gathers one segment ahead
+    int fwd_prefetch = 1;         // forward projector gathers 0, 1 or 2 segments ahead
     int fwd_lane_u = 16;          // forward wave patch: lane_u x (64 / lane_u) rays (64, 32 or 16)
     int fwd_wave_angles = 4;      // angles per forward workgroup: 1 (64 x 4 pixels) or 4 (one patch)
     int fwd_angle_block = 8;      // forward work order: angles per block (4, 8, 16 or 32)

@@ -456,6 +456,7 @@ __global__ __launch_bounds__(256) void k_backward_rays(const TP *__restrict__ pr
 
     for (int e = threadIdx.x; e < BR_COPIES * BR_VOX; e += 256) (&sums[0][0])[e] = 0.f;
 
+    unsigned pass = 0;
     for (int cb = a_begin; cb < a_end; cb += BR_FP) {
         const int ce = min(cb + BR_FP, a_end);
         __syncthreads(); // the previous chunk's footprints are no longer read
@@ -465,31 +466,45 @@ __global__ __launch_bounds__(256) void k_backward_rays(const TP *__restrict__ pr
         }
         __syncthreads();
         for (int a = cb; a < ce;) {
-            // Pack up to BR_COPIES consecutive angles whose footprints hold at
-            // most 256 rays together (a larger single footprint takes a pass
-            // of its own, in rounds of 256).  Uniform over the workgroup.
-            int pre1 = 1 << 30, pre2 = 1 << 30, pre3 = 1 << 30, tot = 0, m = 0;
+            // Pack up to BR_COPIES consecutive angles, m of them, such that m
+            // times the largest footprint is at most 256 rays (a larger single
+            // footprint takes a pass of its own, in rounds of 256).  Uniform
+            // over the workgroup.
+            int m = 0, nmax = 0;
 #pragma unroll
             for (int q = 0; q < BR_COPIES; ++q) {
                 if (a + q >= ce) break;
                 const int4 f = fps[a + q - cb];
                 const int n = max(0, f.y - f.x + 1) * max(0, f.w - f.z + 1);
-                if (q > 0 && tot + n > 256) break;
-                if (q == 1) pre1 = tot;
-                if (q == 2) pre2 = tot;
-                if (q == 3) pre3 = tot;
-                tot += n;
+                if (q > 0 && (q + 1) * max(nmax, n) > 256) break;
+                nmax = max(nmax, n);
                 m = q + 1;
             }
-            for (int t = threadIdx.x; t < tot; t += 256) {
-                const int q = int(t >= pre1) + int(t >= pre2) + int(t >= pre3);
-                const int qs = q == 0 ? 0 : (q == 1 ? pre1 : (q == 2 ? pre2 : pre3));
+            // Lane t takes ray e = t / m of angle a + t mod m, so that each
+            // wave holds the same ranks of all the pass's angles.  Within an
+            // angle the rays are ranked by column, from the footprint's middle
+            // column outwards (middle, right, left, ...), and by row within a
+            // column.  A ray's path through the tile is longest at the middle
+            // and shortens towards the edges, so a wave's lanes walk paths of
+            // similar length and fewer of them idle while the longest one
+            // finishes.
+            // The wave that takes the middle (longest) ranks rotates from pass
+            // to pass and between workgroups, so that the longest walks do
+            // not always fall on the same SIMD of a CU.
+            const float inv_m = __builtin_amdgcn_rcpf(float(m));
+            const int lane_pos = (threadIdx.x + 64 * int((pass + blockIdx.x) & 3)) & 255;
+            ++pass;
+            for (int t = lane_pos; t < m * nmax; t += 256) {
+                const int e = int((float(t) + 0.5f) * inv_m);
+                const int q = t - e * m;
                 const int aa = a + q;
                 const int4 f = fps[aa - cb];
-                const int pw = f.y - f.x + 1;
-                const int e = t - qs;
-                const int r = int((float(e) + 0.5f) * __builtin_amdgcn_rcpf(float(pw)));
-                const int iu = f.x + (e - r * pw), iv = f.z + r;
+                const int pw = f.y - f.x + 1, ph = f.w - f.z + 1;
+                if (pw <= 0 || ph <= 0 || e >= pw * ph) continue;
+                const int rank = int((float(e) + 0.5f) * __builtin_amdgcn_rcpf(float(ph)));
+                const int row = e - rank * ph;
+                const int col = (pw - 1) / 2 + ((rank & 1) ? (rank + 1) >> 1 : -(rank >> 1));
+                const int iu = f.x + col, iv = f.z + row;
                 const int64_t pix = int64_t(iv) * g.nu + iu;
                 const float yv = to_f32(proj[int64_t(aa) * g.nv * g.nu + pix]) * dlen[pix];
                 if (yv == 0.f) continue;

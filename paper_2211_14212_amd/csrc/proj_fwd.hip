@@ -102,7 +102,7 @@ __device__ inline double one_if(bool c)
 
 // One workgroup tile (logical workgroup index `logical`): 64 x 4 pixels of
 // one angle, or a lane_u x (64 / lane_u) patch at 4 angles.
-template <typename TV, typename TP, typename OFF, bool PREFETCH>
+template <typename TV, typename TP, typename OFF, int DEPTH>
 __device__ inline void fwd_tile(const TV *__restrict__ vpad, TP *__restrict__ proj, const AngleGeo *__restrict__ tab,
                                 const GeoParams &g, const PadLayout &pl, int tiles_u, int tiles_v, int lane_u,
                                 int wave_angles, int angle_block, int64_t logical,
@@ -207,7 +207,63 @@ __device__ inline void fwd_tile(const TV *__restrict__ vpad, TP *__restrict__ pr
             // most nx+ny+nz+3 crossings.  Every access stays inside the padded
             // copy: indices start inside the volume and at most one step per
             // axis can land on the zero border before tc reaches tmax.
-            if constexpr (PREFETCH) {
+            if constexpr (DEPTH == 2) {
+                // Two gathers in flight.  The walker runs one voxel ahead of
+                // the sums: while the segment of voxel n is added, the values
+                // of voxels n+1 and n+2 are on their way.  Three registers
+                // rotate through an unrolled trip and hold the raw stored
+                // values (a conversion right after a load would wait for it),
+                // so no register is copied while its load is pending.  The
+                // trip has no per-lane exit: a lane that has reached tmax stays
+                // in the loop with its sums frozen until every lane of the
+                // wave has, so the loop's only branch is wave-uniform and each
+                // use waits for its own load only.  The walker steps only
+                // while the current voxel's exit lies before tmax (the rule
+                // of the loops below, which keeps every index inside the
+                // padded copy); otherwise the load repeats the current voxel.
+                // Segments are added in the same order with the same
+                // operations as the one-ahead loop: the sums are bitwise
+                // equal.
+                TV r0 = *reinterpret_cast<const TV *>(vb + off), r1 = r0, r2 = r0;
+                double ta = tc, tb;
+                bool alive;
+                {
+                    const double m1 = fmin(tx, ty);
+                    tb = fmin(m1, tz);
+                    alive = tb < tmax;
+                    const bool xy = tx <= ty, first = m1 <= tz;
+                    tx = fma(one_if(alive && xy && first), dtx, tx);
+                    ty = fma(one_if(alive && !xy && first), dty, ty);
+                    tz = fma(one_if(alive && !first), dtz, tz);
+                    off += alive ? (first ? (xy ? stx : sty) : stz) : OFF(0);
+                    r1 = *reinterpret_cast<const TV *>(vb + off);
+                    if (!alive) acc = fmaf(float(tmax - ta), to_f32(r0), acc);
+                }
+#define KCT_FWD2_STEP(R0, R1, R2)                                                                          \
+    {                                                                                                      \
+        const double m1 = fmin(tx, ty);                                                                    \
+        const double tcx = fmin(m1, tz);                                                                   \
+        const bool more = alive && tcx < tmax;                                                             \
+        const bool xy = tx <= ty, first = m1 <= tz;                                                        \
+        tx = fma(one_if(more && xy && first), dtx, tx);                                                    \
+        ty = fma(one_if(more && !xy && first), dty, ty);                                                   \
+        tz = fma(one_if(more && !first), dtz, tz);                                                         \
+        off += more ? (first ? (xy ? stx : sty) : stz) : OFF(0);                                           \
+        R2 = *reinterpret_cast<const TV *>(vb + off);                                                      \
+        const float s0 = fmaf(float(tb - ta), to_f32(R0), acc);                                            \
+        const float s1 = fmaf(float(tmax - tb), to_f32(R1), s0);                                           \
+        acc = alive ? (more ? s0 : s1) : acc;                                                              \
+        alive = more;                                                                                      \
+        ta = tb;                                                                                           \
+        tb = tcx;                                                                                          \
+    }
+                while (__any(alive)) {
+                    KCT_FWD2_STEP(r0, r1, r2)
+                    KCT_FWD2_STEP(r1, r2, r0)
+                    KCT_FWD2_STEP(r2, r0, r1)
+                }
+#undef KCT_FWD2_STEP
+            } else if constexpr (DEPTH == 1) {
                 // Two segments per trip, so the voxel value is requested a
                 // whole step before its FMA and no register is copied.  Each
                 // step advances exactly one axis, the one whose crossing comes
@@ -287,7 +343,7 @@ __device__ inline void fwd_tile(const TV *__restrict__ vpad, TP *__restrict__ pr
 // (b mod 8) on every pass; the logical tile is (b mod 8) * g8 + b / 8, so each
 // XCD works through one contiguous eighth of the tiles (neighbouring angles
 // and detector rows share its L2).
-template <typename TV, typename TP, typename OFF, bool PREFETCH>
+template <typename TV, typename TP, typename OFF, int DEPTH>
 __global__ __launch_bounds__(256) void k_forward(const TV *__restrict__ vpad, TP *__restrict__ proj,
                                                  const AngleGeo *__restrict__ tab, GeoParams g, PadLayout pl,
                                                  int tiles_u, int tiles_v, int lane_u, int wave_angles,
@@ -300,7 +356,7 @@ __global__ __launch_bounds__(256) void k_forward(const TV *__restrict__ vpad, TP
     for (int64_t b = blockIdx.x; b < launch; b += gridDim.x) {
         const int64_t logical = (b & 7) * g8 + (b >> 3);
         if (logical >= groups) continue;
-        fwd_tile<TV, TP, OFF, PREFETCH>(vpad, proj, tab, g, pl, tiles_u, tiles_v, lane_u, wave_angles, angle_block,
+        fwd_tile<TV, TP, OFF, DEPTH>(vpad, proj, tab, g, pl, tiles_u, tiles_v, lane_u, wave_angles, angle_block,
                                          logical, ep, red);
         __syncthreads(); // red[] is reused by the next tile's reduction
     }
@@ -342,11 +398,13 @@ kct_status fwd_typed(Plan &p, const void *pad, void *proj, const Epilogue &ep, h
                        static_cast<TP *>(proj), p.d_tab, p.gp, p.pad, tiles_u, tiles_v, p.fwd_lane_u,                 \
                        p.fwd_wave_angles, p.fwd_angle_block, groups, launch, ep)
     if (small) {
-        if (p.fwd_prefetch) KCT_FWD_LAUNCH(uint32_t, true);
-        else KCT_FWD_LAUNCH(uint32_t, false);
+        if (p.fwd_prefetch == 2) KCT_FWD_LAUNCH(uint32_t, 2);
+        else if (p.fwd_prefetch == 1) KCT_FWD_LAUNCH(uint32_t, 1);
+        else KCT_FWD_LAUNCH(uint32_t, 0);
     } else {
-        if (p.fwd_prefetch) KCT_FWD_LAUNCH(uint64_t, true);
-        else KCT_FWD_LAUNCH(uint64_t, false);
+        if (p.fwd_prefetch == 2) KCT_FWD_LAUNCH(uint64_t, 2);
+        else if (p.fwd_prefetch == 1) KCT_FWD_LAUNCH(uint64_t, 1);
+        else KCT_FWD_LAUNCH(uint64_t, 0);
     }
 #undef KCT_FWD_LAUNCH
     return check_hip(hipGetLastError(), "forward projection launch");

@@ -109,19 +109,21 @@ def test_bitwise_deterministic(kct):
 
 @pytest.mark.parametrize("name", ["ragged", "face_planes", "muct_crop"])
 def test_forward_gather_depths_agree_bitwise(kct, name, monkeypatch):
-    """The forward loop with and without the one-step-ahead gather
-    (KCT_FWD_PREFETCH, read at plan creation) loads the same voxels and adds
-    the same segments in the same order: the projections are bitwise equal."""
+    """The forward loop gathering 0, 1 or 2 segments ahead (KCT_FWD_PREFETCH,
+    read at plan creation) loads the same voxels and adds the same segments
+    in the same order: the projections are bitwise equal, for FP32 and FP16
+    storage."""
     gd = _geoms()[name]
     x = torch.from_numpy(synth.random_volume(tuple(gd[k] for k in ("nz", "ny", "nx")), 7)).to(DEV)
     outs = []
-    for depth in ("0", "1"):
+    for depth in ("0", "1", "2"):
         monkeypatch.setenv("KCT_FWD_PREFETCH", depth)
         plan = kct.Plan(kct.Geometry.from_dict(gd))
-        outs.append(plan.forward(x))
+        outs.append((plan.forward(x), plan.forward(x.half())))
         torch.cuda.synchronize()
         plan.close()
-    assert torch.equal(outs[0], outs[1])
+    for o in outs[1:]:
+        assert torch.equal(outs[0][0], o[0]) and torch.equal(outs[0][1], o[1])
 
 
 @pytest.mark.parametrize("name,lanes", [("ragged", "16"), ("ragged", "64"), ("face_planes", "32"), ("muct_crop", "16")])
