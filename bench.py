@@ -445,9 +445,16 @@ def serving_leg(args, torch):
     log("[bench] serving stream")
     torch.cuda.empty_cache()
     reqs = serve.make_requests(args.serve_requests, 2.0, seed=5, size_scale=args.serve_scale)
-    batched = serve.summarize(serve.Server(200e9, keep_results=False).run(reqs), rate=2.0)
+    srv = serve.Server(200e9, keep_results=False)
+    batched = serve.summarize(srv.run(reqs))
     serial = serve.summarize(serve.serve_serial(reqs, keep_results=False), rate=2.0)
+    # The offered load: arrival rate x mean service time of a request alone
+    # on the GPU (the serial path's solve times).
+    rho = serial.pop("offered_load_rho")
     out = {"requests": args.serve_requests, "rate_per_s": 2.0, "size_scale": args.serve_scale,
+           "offered_load_rho": round(rho, 3),
+           "admission": f"{srv.policy}, {srv.max_active} active, fillers up to {srv.filler_frac} of the "
+                        "first-come request's work, 2 iterations in flight each",
            "batched": {k: round(v, 4) for k, v in batched.items()},
            "serial": {k: round(v, 4) for k, v in serial.items()}}
     log(f"[bench] serving {out}")

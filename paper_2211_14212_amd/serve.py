@@ -17,7 +17,12 @@ same as a solo kct_solve of it (deterministic kernels, private buffers).
 Admission is first-come first-served by default; ``policy="sjf"`` admits the
 queued request with the least work first (ray-iterations, the cost of its
 projector calls), which shortens typical latency when the stream outruns
-the GPU, at the expense of the largest requests.
+the GPU, at the expense of the largest requests; ``policy="mixed"`` keeps one
+slot first-come first-served (the oldest queued request is always the next
+to run in it, so no request waits behind an endless supply of smaller ones)
+and fills the other slots shortest-job-first with requests whose work is at
+most ``filler_frac`` of the first-come request's, which then run beside it
+without slowing it much (their kernels are small).
 A request can be cancelled (``Server.cancel``): no further iteration of it is
 enqueued, and once its last enqueued one has run its memory is freed and it
 returns a result marked ``cancelled`` with no image.  The other requests are
@@ -80,6 +85,7 @@ class _Active:
         self.nbytes, self.admitted = nbytes, admitted
         self.events: deque = deque()  # one per enqueued step not yet seen complete
         self.enqueued = 0
+        self.fifo_slot = False  # admitted to the first-come first-served slot ("mixed")
 
     def drain(self) -> None:
         """Forget the steps the device has finished."""
@@ -101,20 +107,23 @@ def request_bytes(plan: Plan, req: Request) -> int:
 
 
 class Server:
-    def __init__(self, budget_bytes: float = 200e9, device: int = 0, max_active: int = 16,
-                 keep_results: bool = True, verbose: bool = False, policy: str = "fifo", depth: int = 2):
-        if policy not in ("fifo", "sjf"):
+    def __init__(self, budget_bytes: float = 200e9, device: int = 0, max_active: int = 3,
+                 keep_results: bool = True, verbose: bool = False, policy: str = "mixed", depth: int = 2,
+                 filler_frac: float = 0.5):
+        if policy not in ("fifo", "sjf", "mixed"):
             raise ValueError(policy)
         if depth < 1:
             raise ValueError("depth must be at least 1")
         self.policy = policy
         self.depth = depth
+        self.filler_frac = filler_frac
         self.budget = int(budget_bytes)
         self.device = torch.device("cuda", device)
         self.max_active = max_active
         self.keep_results = keep_results
         self.verbose = verbose
         self.log = []
+        self.fifo_log: list[int] = []  # ids admitted to the first-come slot ("mixed"), in order
         self._cancel: set[int] = set()
 
     def cancel(self, req_id: int) -> None:
@@ -165,7 +174,12 @@ class Server:
                 # of the queue (FIFO) or the least work (SJF, ties by arrival),
                 # once its plan is ready.
                 while queue and len(active) < self.max_active:
-                    i = 0 if self.policy == "fifo" else min(range(len(queue)), key=lambda k: request_work(queue[k]))
+                    head = next((a for a in active if a.fifo_slot), None)
+                    fifo_turn = self.policy == "fifo" or (self.policy == "mixed" and head is None)
+                    i = 0 if fifo_turn else min(range(len(queue)), key=lambda k: request_work(queue[k]))
+                    if (self.policy == "mixed" and not fifo_turn and
+                            request_work(queue[i]) > self.filler_frac * request_work(head.req)):
+                        break
                     req = queue[i]
                     if not plans[req.id].done():
                         break
@@ -187,6 +201,9 @@ class Server:
                     state = plan.state(req.b, req.solver, req.n_iter, req.lam, req.vec_dtype, stream=stream)
                     used += need
                     a = _Active(req, plan, state, stream, need, time.perf_counter() - t0)
+                    a.fifo_slot = self.policy == "mixed" and fifo_turn
+                    if a.fifo_slot:
+                        self.fifo_log.append(req.id)
                     active.append(a)
                     self.log.append(("admit", req.id, a.admitted, used))
                 # Keep up to `depth` iterations of every active request enqueued.
@@ -353,20 +370,22 @@ def main(argv=None):
     ap.add_argument("--rate", type=float, default=2.0)
     ap.add_argument("--size-scale", type=float, default=1.0)
     ap.add_argument("--budget-gb", type=float, default=200.0)
-    ap.add_argument("--max-active", type=int, default=16)
+    ap.add_argument("--max-active", type=int, default=3)
     ap.add_argument("--no-serial", action="store_true")
     ap.add_argument("--sjf", action="store_true", help="also serve the stream with shortest-job-first admission")
+    ap.add_argument("--policy", default="mixed", choices=("fifo", "sjf", "mixed"), help="admission of the batched run")
     args = ap.parse_args(argv)
     print("[serve] generating requests", file=sys.stderr, flush=True)
     reqs = make_requests(args.requests, args.rate, size_scale=args.size_scale)
     work = sum(r.n_iter * r.geom.n_rays for r in reqs)
     print(f"[serve] {len(reqs)} requests, {work / 1e9:.1f} G ray-iterations", file=sys.stderr, flush=True)
-    srv = Server(args.budget_gb * 1e9, max_active=args.max_active, keep_results=False, verbose=True)
+    srv = Server(args.budget_gb * 1e9, max_active=args.max_active, keep_results=False, verbose=True,
+                 policy=args.policy)
     res = srv.run(reqs)
     out = {"batched": summarize(res)}
     print(f"[serve] batched {out['batched']}", file=sys.stderr, flush=True)
     if args.sjf:
-        sjf = Server(args.budget_gb * 1e9, max_active=args.max_active, keep_results=False, verbose=True,
+        sjf = Server(args.budget_gb * 1e9, max_active=16, keep_results=False, verbose=True,
                      policy="sjf").run(reqs)
         out["batched_sjf"] = summarize(sjf)
         print(f"[serve] batched, shortest job first {out['batched_sjf']}", file=sys.stderr, flush=True)

@@ -24,7 +24,7 @@ def stream(gpu_lib):
 
 def test_mix_equals_alone(stream):
     serve, reqs = stream
-    srv = serve.Server(budget_bytes=50e9, max_active=6)
+    srv = serve.Server(budget_bytes=50e9, max_active=6, policy="fifo")
     res = srv.run(reqs)
     assert len(res) == len(reqs)
     overlap = any(a[0] == "admit" and a[3] > 0 for a in srv.log)
@@ -56,6 +56,26 @@ def test_sjf_admission_results_bitwise(stream):
     assert sorted(admits) == sorted(r.id for r in reqs)
 
 
+def test_mixed_admission_results_bitwise(stream):
+    """The default admission (one first-come slot, the others filled
+    shortest-first with requests of at most half the first-come request's
+    work) changes the order, not the results; the first-come slot takes the
+    requests it runs in arrival order."""
+    serve, reqs = stream
+    srv = serve.Server(budget_bytes=50e9, max_active=3, policy="mixed", filler_frac=0.5)
+    res = srv.run(reqs)
+    assert len(res) == len(reqs) and not any(r.cancelled or r.rejected for r in res)
+    for req, r in zip(reqs, res):
+        plan = serve.Plan(req.geom)
+        x, h = plan.solve(req.b, req.solver, req.n_iter, req.lam)
+        torch.cuda.synchronize()
+        assert torch.equal(r.x, x), req.id
+        assert torch.equal(r.history, h), req.id
+    fifo = srv.fifo_log
+    arrival = {r.id: r.arrival for r in reqs}
+    assert fifo and all(arrival[a] <= arrival[b] for a, b in zip(fifo, fifo[1:]))
+
+
 def test_budget_respected(stream):
     serve, reqs = stream
     plans = [serve.Plan(r.geom) for r in reqs]
@@ -63,7 +83,7 @@ def test_budget_respected(stream):
     for p in plans:
         p.close()
     budget = 2.2 * max(sizes)
-    srv = serve.Server(budget_bytes=budget, max_active=8, keep_results=False)
+    srv = serve.Server(budget_bytes=budget, max_active=8, keep_results=False, policy="fifo")
     res = srv.run(reqs)
     assert len(res) == len(reqs)
     assert max(u for (_, _, _, u) in srv.log) <= budget
@@ -81,7 +101,7 @@ def test_oversized_request_rejected(stream):
     budget = 1.01 * sorted(sizes)[len(sizes) // 2]
     big = {r.id for r, n in zip(reqs, sizes) if n > budget}
     assert big and len(big) < len(reqs)
-    srv = serve.Server(budget_bytes=budget, max_active=8, keep_results=False)
+    srv = serve.Server(budget_bytes=budget, max_active=8, keep_results=False, policy="fifo")
     res = srv.run(reqs)
     for r in res:
         assert r.rejected == (r.id in big) and not r.cancelled, r.id
@@ -93,7 +113,7 @@ def test_oversized_request_rejected(stream):
 def test_cancel_leaves_others_bitwise(stream):
     serve, reqs = stream
     victim, early = reqs[1].id, reqs[-1].id
-    srv = serve.Server(budget_bytes=50e9, max_active=6)
+    srv = serve.Server(budget_bytes=50e9, max_active=6, policy="fifo")
     srv.cancel(early)  # cancelled before it is ever stepped
     res = srv.run(reqs, cancel_after={victim: 2})
     assert len(res) == len(reqs)
