@@ -400,6 +400,15 @@ __global__ __launch_bounds__(256) void k_backward(const TP *__restrict__ proj, T
 // ---------------------------------------------------------------------------
 constexpr int BR_TX = 16, BR_TY = 16, BR_TZ = 8;     // voxel tile
 constexpr int BR_VOX = BR_TX * BR_TY * BR_TZ;        // 2048 sums per copy
+// LDS layout of a copy: z-layers 257 floats apart and copies 2064 floats
+// apart (16 banks apart).  Rays that walk in lockstep through the same
+// (i, j) cells meet them at other z-layers (neighbouring detector rows) or
+// in other copies (neighbouring angles); with a 256-float layer stride all
+// of those sums would sit in one LDS bank and every read and write of the
+// wave would serialise on it.
+constexpr int BR_KS = BR_TX * BR_TY + 1;              // z-layer stride
+constexpr int BR_CS = BR_TZ * BR_KS + 8;              // copy stride (2064)
+constexpr int BR_LAST = (BR_TZ - 1) * BR_KS + BR_TX * BR_TY - 1; // last cell of a copy
 constexpr int BR_COPIES = 4;                         // angles side by side
 constexpr int BR_FP = 64;                            // tile footprints kept in LDS at a time
 // Segments shorter than this (in units of the whole source-pixel ray) are
@@ -424,7 +433,7 @@ __global__ __launch_bounds__(256) void k_backward_rays(const TP *__restrict__ pr
 {
     const int chunks = int(gridDim.y), chunk = int(blockIdx.y);
     const int a_begin = int(int64_t(g.na) * chunk / chunks), a_end = int(int64_t(g.na) * (chunk + 1) / chunks);
-    __shared__ float sums[BR_COPIES][BR_VOX];
+    __shared__ float sums[BR_COPIES][BR_CS];
     __shared__ float junk_cell[1]; // sink of the walk's skipped segments (never read back)
     __shared__ int4 fps[BR_FP];
     __shared__ double red[4];
@@ -454,7 +463,7 @@ __global__ __launch_bounds__(256) void k_backward_rays(const TP *__restrict__ pr
     const float tz0 = float(g.Z0 + k0 * g.vz), tz1 = float(g.Z0 + ke * g.vz);
     const float margin = 0.01f; // pixels: the footprint only enumerates candidate rays
 
-    for (int e = threadIdx.x; e < BR_COPIES * BR_VOX; e += 256) (&sums[0][0])[e] = 0.f;
+    for (int e = threadIdx.x; e < BR_COPIES * BR_CS; e += 256) (&sums[0][0])[e] = 0.f;
 
     unsigned pass = 0;
     for (int cb = a_begin; cb < a_end; cb += BR_FP) {
@@ -554,9 +563,9 @@ __global__ __launch_bounds__(256) void k_backward_rays(const TP *__restrict__ pr
                 else if (dx < 0.0) { txc = (i - A.svx) * inx; dtx = -inx; sx = -1; }
                 if (dy > 0.0) { tyc = (j + 1 - A.svy) * iny; dty = iny; sy = BR_TX; }
                 else if (dy < 0.0) { tyc = (j - A.svy) * iny; dty = -iny; sy = -BR_TX; }
-                if (dz > 0.0) { tzc = (k + 1 - A.svz) * inz; dtz = inz; sz = BR_TX * BR_TY; }
-                else if (dz < 0.0) { tzc = (k - A.svz) * inz; dtz = -inz; sz = -BR_TX * BR_TY; }
-                int off = ((k - k0) * BR_TY + (j - j0)) * BR_TX + (i - i0);
+                if (dz > 0.0) { tzc = (k + 1 - A.svz) * inz; dtz = inz; sz = BR_KS; }
+                else if (dz < 0.0) { tzc = (k - A.svz) * inz; dtz = -inz; sz = -BR_KS; }
+                int off = (k - k0) * BR_KS + (j - j0) * BR_TX + (i - i0);
                 double tc = tmin;
                 // Each step ends the current segment at the first crossing
                 // (or the exit) and advances exactly one axis, x before y
@@ -578,7 +587,7 @@ __global__ __launch_bounds__(256) void k_backward_rays(const TP *__restrict__ pr
         const bool xy = txc <= tyc, first = m1 <= tzc;                                                     \
         float *dst = acc + off;                                                                            \
         off += first ? (xy ? sx : sy) : sz;                                                                \
-        NEXT = acc[min(max(off, 0), BR_VOX - 1)];                                                          \
+        NEXT = acc[min(max(off, 0), BR_LAST)];                                                             \
         txc = fma(br_one_if(xy && first), dtx, txc);                                                       \
         tyc = fma(br_one_if(!xy && first), dty, tyc);                                                      \
         tzc = fma(br_one_if(!first), dtz, tzc);                                                            \
@@ -588,7 +597,7 @@ __global__ __launch_bounds__(256) void k_backward_rays(const TP *__restrict__ pr
         if (!(t1 < tmax)) break;                                                                           \
         tc = t1;                                                                                           \
     }
-                float ca = acc[min(max(off, 0), BR_VOX - 1)], cb;
+                float ca = acc[min(max(off, 0), BR_LAST)], cb;
                 for (;;) {
                     KCT_BR_STEP(ca, cb)
                     KCT_BR_STEP(cb, ca)
@@ -608,7 +617,8 @@ __global__ __launch_bounds__(256) void k_backward_rays(const TP *__restrict__ pr
         const int li = l % BR_TX, lj = (l / BR_TX) % BR_TY, lk = l / (BR_TX * BR_TY);
         const int i = i0 + li, j = j0 + lj, k = k0 + lk;
         if (i >= ie || j >= je || k >= ke) continue;
-        const float a_k = ((sums[0][l] + sums[1][l]) + sums[2][l]) + sums[3][l];
+        const int c = lk * BR_KS + lj * BR_TX + li;
+        const float a_k = ((sums[0][c] + sums[1][c]) + sums[2][c]) + sums[3][c];
         const int64_t idx = (int64_t(k) * g.ny + j) * g.nx + i;
         if (chunks > 1) {
             ep.split[int64_t(chunk) * g.nx * g.ny * g.nz + idx] = a_k;

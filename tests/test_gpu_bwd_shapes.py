@@ -99,3 +99,22 @@ def test_backward_default_shape_mid_volume(kct, monkeypatch):
     print("[bwd shape] mid192 default", flush=True)
     shape = _check(kct, _geoms()["mid192"], 212)
     assert shape["kz"] == 8 and shape["split"] == 1 and shape["rays"] == 0
+
+
+def test_ray_backprojector_bitwise_deterministic(kct, monkeypatch):
+    """The ray-driven kernel adds every voxel's terms in a fixed order (angle
+    order within each of its four copies of the tile sums, then the copies in
+    order): two runs give the same bits, with and without the angle split."""
+    for var in ("KCT_BWD_KZ", "KCT_BWD_ACC", "KCT_BWD_RAYS"):
+        monkeypatch.delenv(var, raising=False)
+    gd = _geoms()["muct_crop"]
+    y = torch.from_numpy(synth.random_projections(tuple(
+        (len(gd["angles"]), gd["nv"], gd["nu"])), 213)).to(DEV)
+    for split in ("1", "16"):
+        monkeypatch.setenv("KCT_BWD_SPLIT", split)
+        plan = kct.Plan(kct.Geometry.from_dict(gd))
+        assert plan.bwd_shape()["rays"] == 1
+        a, b = plan.backproject(y), plan.backproject(y)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), split
+        plan.close()
