@@ -363,11 +363,19 @@ def headline(args, torch, kct, synth):
                     tv_outer=n_outer, tv_inner=n_inner, tv_eps=eps)
     st.step(args.warmup)
     torch.cuda.synchronize()
+    log(f"[bench] warm-up done; timing {args.steps} iterations")
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    marks = [torch.cuda.Event() for _ in range(args.steps)]
     e0.record(st.stream)
-    for _ in range(args.steps):
+    for k in range(args.steps):
         st.step(1)
+        marks[k].record(st.stream)
     e1.record(st.stream)
+    # Every iteration is enqueued before the host waits: the waits below only
+    # report progress (one line per finished iteration), the device never idles.
+    for k, m in enumerate(marks):
+        m.synchronize()
+        log(f"[bench]   iteration {k + 1}/{args.steps} done")
     torch.cuda.synchronize()
     step_ms = e0.elapsed_time(e1) / args.steps
     hist = st.history.cpu().numpy()[:args.warmup + args.steps]
@@ -445,9 +453,9 @@ def serving_leg(args, torch):
     log("[bench] serving stream")
     torch.cuda.empty_cache()
     reqs = serve.make_requests(args.serve_requests, 2.0, seed=5, size_scale=args.serve_scale)
-    srv = serve.Server(200e9, keep_results=False)
+    srv = serve.Server(200e9, keep_results=False, verbose=True)
     batched = serve.summarize(srv.run(reqs))
-    serial = serve.summarize(serve.serve_serial(reqs, keep_results=False), rate=2.0)
+    serial = serve.summarize(serve.serve_serial(reqs, keep_results=False, verbose=True), rate=2.0)
     # The offered load: arrival rate x mean service time of a request alone
     # on the GPU (the serial path's solve times).
     rho = serial.pop("offered_load_rho")
