@@ -248,7 +248,8 @@ typedef enum kct_solver {
                             preconditioner E (L_k D)^+ (the A-weighted
                             pseudoinverse; E removes the A-weighted constant
                             part, x0 is the best constant), with (L_k D)^+
-                            applied by tv_inner CG steps on D^T L_k^2 D.  Stores
+                            applied by tv_inner FP64 CG steps on D^T L_k^2 D
+                            (four FP64 volumes of work space).  Stores
                             n_iter gradient-space vectors (3 volumes each), n_iter
                             volumes and n_iter+1 projections; lambda_k fixed or
                             chosen per iteration (kct_lambda_rule); FP32 only */

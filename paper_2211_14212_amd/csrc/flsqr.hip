@@ -9,7 +9,11 @@
 // K^+ is applied by CG from zero on the complement of the constants, where K
 // is SPD: every step removes the mean of the residual (folded into the
 // direction update), so rounding cannot drive the iterate along the null
-// space.  D is the forward difference with a zero last difference per axis,
+// space.  The CG's vectors and stencil arithmetic are FP64: with weights near
+// 1/sqrt(eps) in flat regions K is badly conditioned, and an FP32 CG moved
+// the 4th fLSQR-TV iterate of the 32^3 workload at eps = 1e-3 by 1.1e-3 in
+// oracle runs, five times the effect of FP32 rounding of the matvecs.  Its
+// right-hand side arrives in FP32 and its result leaves in FP32.  D is the forward difference with a zero last difference per axis,
 // as in IRN-TV.  Volumes are x-fastest; gradient-space vectors are planar
 // (component c of voxel e at c*M + e).  The vector kernels are one thread per
 // voxel in a grid-stride loop, the stencils one workgroup per x-row; all are
@@ -60,8 +64,8 @@ __device__ inline bool finite(double v) { return v == v && v - v == 0.0; }
 // each XCD walks one contiguous eighth of the rows, so the z neighbours of a
 // row (one slice away) are mostly read through the same L2.
 
-__global__ __launch_bounds__(256) void k_fl_lap(const float *__restrict__ p, const float *__restrict__ Lw, Dims d,
-                                                float *__restrict__ q, double *parts)
+__global__ __launch_bounds__(256) void k_fl_lap(const double *__restrict__ p, const float *__restrict__ Lw, Dims d,
+                                                double *__restrict__ q, double *parts)
 {
     __shared__ double red[4];
     const int64_t sxy = int64_t(d.nx) * d.ny;
@@ -80,11 +84,11 @@ __global__ __launch_bounds__(256) void k_fl_lap(const float *__restrict__ p, con
         for (int i = threadIdx.x; i < d.nx; i += 256) {
             const int64_t e = e0 + i;
             const int64_t dxp = i < d.nx - 1 ? 1 : 0, dxm = i > 0 ? 1 : 0;
-            const float c = p[e], le = Lw[e], we = le * le;
-            const float pxp = p[e + dxp], pxm = p[e - dxm], pyp = p[e + dyp], pym = p[e - dym];
-            const float pzp = p[e + dzp], pzm = p[e - dzm];
-            const float lx = Lw[e - dxm], ly = Lw[e - dym], lz = Lw[e - dzm];
-            float t = 0.f;
+            const double c = p[e], le = Lw[e], we = le * le;
+            const double pxp = p[e + dxp], pxm = p[e - dxm], pyp = p[e + dyp], pym = p[e - dym];
+            const double pzp = p[e + dzp], pzm = p[e - dzm];
+            const double lx = Lw[e - dxm], ly = Lw[e - dym], lz = Lw[e - dzm];
+            double t = 0.0;
             t -= we * (pxp - c);
             t += lx * lx * (c - pxm);
             t -= we * (pyp - c);
@@ -92,15 +96,15 @@ __global__ __launch_bounds__(256) void k_fl_lap(const float *__restrict__ p, con
             t -= we * (pzp - c);
             t += lz * lz * (c - pzm);
             q[e] = t;
-            acc += double(c) * double(t);
+            acc += c * t;
         }
     }
     acc = block_sum(acc, red);
     if (threadIdx.x == 0) parts[blockIdx.x] = acc;
 }
 
-__global__ __launch_bounds__(256) void k_fl_cg_update(float *__restrict__ t, float *__restrict__ r,
-                                                      const float *__restrict__ p, const float *__restrict__ q,
+__global__ __launch_bounds__(256) void k_fl_cg_update(double *__restrict__ t, double *__restrict__ r,
+                                                      const double *__restrict__ p, const double *__restrict__ q,
                                                       int64_t n, const double *S, double *psum, double *psq)
 {
     __shared__ double red[4];
@@ -108,11 +112,11 @@ __global__ __launch_bounds__(256) void k_fl_cg_update(float *__restrict__ t, flo
     double s1 = 0.0, s2 = 0.0;
     FL_LOOP(e, n)
     {
-        t[e] = float(double(t[e]) + alpha * p[e]);
-        const float v = float(double(r[e]) - alpha * q[e]);
+        t[e] = t[e] + alpha * p[e];
+        const double v = r[e] - alpha * q[e];
         r[e] = v;
         s1 += v;
-        s2 += double(v) * v;
+        s2 += v * v;
     }
     s1 = block_sum(s1, red);
     s2 = block_sum(s2, red);
@@ -122,16 +126,31 @@ __global__ __launch_bounds__(256) void k_fl_cg_update(float *__restrict__ t, flo
     }
 }
 
-__global__ __launch_bounds__(256) void k_fl_cg_dir(float *__restrict__ r, float *__restrict__ p, int64_t n,
-                                                   const double *S, int first)
+// First call (rhs given): r = rhs - mu, p = r, t = 0.  Later: r -= mu,
+// p = r + beta p.
+__global__ __launch_bounds__(256) void k_fl_cg_dir(double *__restrict__ r, double *__restrict__ p,
+                                                   double *__restrict__ t, const float *__restrict__ rhs,
+                                                   int64_t n, const double *S)
 {
     const double mu = S[S_CG_MU], beta = S[S_CG_BETA];
     FL_LOOP(e, n)
     {
-        const float v = float(double(r[e]) - mu);
-        r[e] = v;
-        p[e] = first ? v : float(v + beta * p[e]);
+        if (rhs) {
+            const double v = double(rhs[e]) - mu;
+            r[e] = v;
+            p[e] = v;
+            t[e] = 0.0;
+        } else {
+            const double v = r[e] - mu;
+            r[e] = v;
+            p[e] = v + beta * p[e];
+        }
     }
+}
+
+__global__ __launch_bounds__(256) void k_fl_to_f32(float *__restrict__ out, const double *__restrict__ in, int64_t n)
+{
+    FL_LOOP(e, n) out[e] = float(in[e]);
 }
 
 __global__ __launch_bounds__(256) void k_fl_dtl(const float *__restrict__ v3, const float *__restrict__ Lw, Dims d,
@@ -386,24 +405,30 @@ int fl_groups(int64_t n)
 
 #define FL_CHECK(what) return check_hip(hipGetLastError(), what)
 
-kct_status fl_lap(const Plan &p, const float *pv, const float *Lw, float *q, double *parts, hipStream_t st)
+kct_status fl_lap(const Plan &p, const double *pv, const float *Lw, double *q, double *parts, hipStream_t st)
 {
     const Dims d = dims(p);
     hipLaunchKernelGGL(k_fl_lap, dim3(fl_groups(d.M)), dim3(256), 0, st, pv, Lw, d, q, parts);
     FL_CHECK("weighted Laplacian");
 }
 
-kct_status fl_cg_update(float *t, float *r, const float *pv, const float *q, int64_t n, const double *S,
+kct_status fl_cg_update(double *t, double *r, const double *pv, const double *q, int64_t n, const double *S,
                         double *psum, double *psq, hipStream_t st)
 {
     hipLaunchKernelGGL(k_fl_cg_update, dim3(fl_groups(n)), dim3(256), 0, st, t, r, pv, q, n, S, psum, psq);
     FL_CHECK("inner CG update");
 }
 
-kct_status fl_cg_dir(float *r, float *pv, int64_t n, const double *S, bool first, hipStream_t st)
+kct_status fl_cg_dir(double *r, double *pv, double *t, const float *rhs, int64_t n, const double *S, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_fl_cg_dir, dim3(fl_groups(n)), dim3(256), 0, st, r, pv, n, S, first ? 1 : 0);
+    hipLaunchKernelGGL(k_fl_cg_dir, dim3(fl_groups(n)), dim3(256), 0, st, r, pv, t, rhs, n, S);
     FL_CHECK("inner CG direction");
+}
+
+kct_status fl_to_f32(float *out, const double *in, int64_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fl_to_f32, dim3(fl_groups(n)), dim3(256), 0, st, out, in, n);
+    FL_CHECK("inner CG result");
 }
 
 kct_status fl_dtl(const Plan &p, const float *v3, const float *Lw, float *out, double *psum, double *psq,

@@ -20,13 +20,16 @@ static_assert(S_CG_MU < S_COUNT, "scalar block too small");
 
 int fl_groups(int64_t n);
 
+// The inner CG runs in FP64 (vectors and stencil arithmetic).
 // q = D^T (L^2 D p); partial sums of p.q.
-kct_status fl_lap(const Plan &p, const float *pv, const float *Lw, float *q, double *parts, hipStream_t st);
+kct_status fl_lap(const Plan &p, const double *pv, const float *Lw, double *q, double *parts, hipStream_t st);
 // t += alpha p, r -= alpha q; partial sums of r and r^2.
-kct_status fl_cg_update(float *t, float *r, const float *pv, const float *q, int64_t n, const double *S,
+kct_status fl_cg_update(double *t, double *r, const double *pv, const double *q, int64_t n, const double *S,
                         double *psum, double *psq, hipStream_t st);
-// r -= mu; p = r (first) or r + beta p.
-kct_status fl_cg_dir(float *r, float *pv, int64_t n, const double *S, bool first, hipStream_t st);
+// With rhs (FP32): r = rhs - mu, p = r, t = 0.  Without: r -= mu, p = r + beta p.
+kct_status fl_cg_dir(double *r, double *pv, double *t, const float *rhs, int64_t n, const double *S, hipStream_t st);
+// out = in rounded to FP32.
+kct_status fl_to_f32(float *out, const double *in, int64_t n, hipStream_t st);
 // out = D^T (L v3) for a gradient-space v3 (planar); partial sums of out and out^2.
 kct_status fl_dtl(const Plan &p, const float *v3, const float *Lw, float *out, double *psum, double *psq,
                   hipStream_t st);

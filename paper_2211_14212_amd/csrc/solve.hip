@@ -215,7 +215,7 @@ Layout layout(const Plan &p, const kct_solve_params &prm)
         L.v[1] = o; o += up(size_t(M) * 4 * 3 * kk);                     // V_1..V_k, gradient space
         L.v[2] = o; o += up(size_t(M) * 4 * kk);                         // Z_1..Z_k
         L.v[3] = o; o += up(size_t(M) * 4);                              // g = A^T A 1
-        L.v[4] = o; o += up(size_t(M) * 4 * 4);                          // inner CG t, r, p, q
+        L.v[4] = o; o += up(size_t(M) * 4 * 2 + size_t(M) * 8 * 4);      // t, r (FP32); inner CG t, r, p, q (FP64)
         L.v[5] = o; o += up(size_t(M) * 4);                              // L weights
         L.gk = o; o += up(sizeof(double) * (kk + 1) * kk * 2);           // M ((k+1) x k), T (k x k)
         L.work = o; o += up(sizeof(double) * ((2 * kk + 1) * (kk + 1) + 5 * kk + 10));
@@ -707,6 +707,11 @@ float *fl_Z(kct_state &s, int i) { return static_cast<float *>(s.v(2)) + size_t(
 float *fl_g(kct_state &s) { return static_cast<float *>(s.v(3)); }
 float *fl_tmp(kct_state &s, int i) { return static_cast<float *>(s.v(4)) + size_t(i) * size_t(s.M()); }
 float *fl_w(kct_state &s) { return static_cast<float *>(s.v(5)); }
+// The inner CG's FP64 vectors, after the two FP32 volumes of v(4).
+double *fl_d(kct_state &s, int i)
+{
+    return reinterpret_cast<double *>(static_cast<float *>(s.v(4)) + 2 * size_t(s.M())) + size_t(i) * size_t(s.M());
+}
 double *fl_Mat(kct_state &s) { return reinterpret_cast<double *>(s.ws + s.L.gk); }
 double *fl_T(kct_state &s) { return fl_Mat(s) + size_t(fl_ldm(s)) * size_t(fl_K(s)); }
 
@@ -736,20 +741,21 @@ kct_status fl_cg(kct_state &s, int64_t nparts)
 {
     Plan &p = *s.plan;
     const int64_t M = s.M();
-    float *t = fl_tmp(s, 0), *r = fl_tmp(s, 1), *pv = fl_tmp(s, 2), *q = fl_tmp(s, 3);
+    // The right-hand side arrives in fl_tmp(s, 1) (FP32); the result leaves in
+    // fl_tmp(s, 0) (FP32); the CG itself runs in FP64.
+    double *t = fl_d(s, 0), *r = fl_d(s, 1), *pv = fl_d(s, 2), *q = fl_d(s, 3);
     const int ng = fl_groups(M);
     KCT_TRY(fl_sc_cg_init(s.S(), red(s, s.pa(), nparts, 0), red(s, s.pb(), nparts, 1), M, s.st));
-    KCT_TRY(vk_fill(t, KCT_F32, M, 0.f, s.st));
-    KCT_TRY(fl_cg_dir(r, pv, M, s.S(), true, s.st));
+    KCT_TRY(fl_cg_dir(r, pv, t, fl_tmp(s, 1), M, s.S(), s.st));
     for (int it = 0; it < s.prm.tv_inner; ++it) {
         KCT_TRY(fl_lap(p, pv, fl_w(s), q, s.pa(), s.st));
         KCT_TRY(fl_sc_cg_alpha(s.S(), red(s, s.pa(), ng, 0), s.st));
         KCT_TRY(fl_cg_update(t, r, pv, q, M, s.S(), s.pa(), s.pb(), s.st));
         if (it + 1 == s.prm.tv_inner) break;
         KCT_TRY(fl_sc_cg_beta(s.S(), red(s, s.pa(), ng, 0), red(s, s.pb(), ng, 1), M, s.st));
-        KCT_TRY(fl_cg_dir(r, pv, M, s.S(), false, s.st));
+        KCT_TRY(fl_cg_dir(r, pv, t, nullptr, M, s.S(), s.st));
     }
-    return KCT_OK;
+    return fl_to_f32(fl_tmp(s, 0), t, M, s.st);
 }
 
 kct_status fl_iter(kct_state &s)
