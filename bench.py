@@ -312,8 +312,21 @@ def roofline_entry(workload, kname, ms, nnz, n_out, es, n_units):
             out["valu"] = {"insts_per_unit": round(ce["valu_insts_per_unit"], 4), "unit": ce["unit"],
                            "achieved": round(rate / 1e9, 1), "peak": VALU_PEAK_GINSTS,
                            "unit_rate": "G wave-instructions/s", "frac": round(rate / 1e9 / VALU_PEAK_GINSTS, 4)}
-            if out["valu"]["frac"] > out["frac"]:
-                out["bound"] = "alu"
+        pipe = ce.get("pipe")
+        if pipe:
+            # The vector memory pipe: texture address (TA) and data (TD) paths
+            # busy as a fraction of active cycles, and L1 tag lookups per
+            # 64-lane gather (rocprofv3 TA/TD/TCP counters).
+            out["gather_pipe"] = {k: pipe[k] for k in ("ta_busy", "td_busy", "l1_tag_lookups_per_gather", "l1_hit")}
+        # What limits the launch: the busiest of HBM (measured bytes against
+        # the peak), VALU issue and the texture data path.
+        cands = {"hbm": out.get("hbm_gbs_measured", 0.0) / HBM_PEAK_GBS}
+        if "valu" in out:
+            cands["valu_issue"] = out["valu"]["frac"]
+        if pipe:
+            cands["vector_memory_pipe"] = pipe["td_busy"]
+        top = max(cands, key=cands.get)
+        out["limiter"] = {"name": top, "busy": round(cands[top], 4)}
     return out
 
 
