@@ -9,9 +9,10 @@
 // Launch shape: each wave traces a compact patch of neighbouring pixels of
 // one angle (16 x 4 by default), so its lanes follow rays that cross the same
 // voxel columns.  By default a workgroup's 4 waves trace the same patch at 4
-// consecutive angles (wave_angles = 4): rays of neighbouring angles through
-// one pixel nearly coincide, so those waves gather the same lines at nearly
-// the same time and the CU's L1 and the XCD's L2 serve them once.  (The
+// consecutive angles (wave_angles = 4; 8 in workgroups of 512 threads for
+// large volumes): rays of neighbouring angles through one pixel nearly
+// coincide, so those waves gather the same lines at nearly the same time and
+// the CU's L1 and the XCD's L2 serve them once.  (The
 // alternative, 4 waves tiling a 64 x 4 pixel block of one angle, is 20 %
 // slower on 256^3 / 360 x 512^2 and 60 % slower on a 1500^3 volume whose
 // gathers then miss L2 half of the time.)  Lanes map to u, and neighbouring u
@@ -71,7 +72,9 @@ __global__ __launch_bounds__(256) void k_pad_volume(const TIN *__restrict__ in, 
     }
 }
 
-// Deterministic workgroup sum of one double per thread (256 threads).
+// Deterministic workgroup sum of one double per thread (256, 512 or 1024
+// threads; `red` holds one double per wave): waves summed in groups of four,
+// the groups in order.
 __device__ inline double block_sum_256(double v, double *red)
 {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -79,7 +82,10 @@ __device__ inline double block_sum_256(double v, double *red)
     if (lane == 0) red[w] = v;
     __syncthreads();
     double s = 0.0;
-    if (threadIdx.x == 0) s = ((red[0] + red[1]) + red[2]) + red[3];
+    if (threadIdx.x == 0) {
+        const int nw = int(blockDim.x) >> 6;
+        for (int q = 0; q < nw; q += 4) s += ((red[q] + red[q + 1]) + red[q + 2]) + red[q + 3];
+    }
     return s;
 }
 
@@ -135,9 +141,9 @@ __device__ inline void fwd_tile(const TV *__restrict__ vpad, TP *__restrict__ pr
         a = ab * angle_block + ai;
         iu = tui * FWD_TU + (wv % waves_u) * lane_u + lane % lane_u;
         iv = tvi * FWD_TV + (wv / waves_u) * rows_w + lane / lane_u;
-    } else { // tiles of one wave patch; wave w takes angle 4 * group + w
+    } else { // tiles of one wave patch; wave w takes angle wave_angles * group + w
         const int tui = r2 / n_at, ag = r2 - tui * n_at;
-        a = ab * angle_block + ag * 4 + wv;
+        a = ab * angle_block + ag * wave_angles + wv;
         iu = tui * lane_u + lane % lane_u;
         iv = tvi * rows_w + lane / lane_u;
     }
@@ -344,13 +350,13 @@ __device__ inline void fwd_tile(const TV *__restrict__ vpad, TP *__restrict__ pr
 // XCD works through one contiguous eighth of the tiles (neighbouring angles
 // and detector rows share its L2).
 template <typename TV, typename TP, typename OFF, int DEPTH>
-__global__ __launch_bounds__(256) void k_forward(const TV *__restrict__ vpad, TP *__restrict__ proj,
+__global__ __launch_bounds__(1024) void k_forward(const TV *__restrict__ vpad, TP *__restrict__ proj,
                                                  const AngleGeo *__restrict__ tab, GeoParams g, PadLayout pl,
                                                  int tiles_u, int tiles_v, int lane_u, int wave_angles,
                                                  int angle_block, int64_t groups, int64_t launch,
                                                  Epilogue ep)
 {
-    __shared__ double red[4];
+    __shared__ double red[16];
     if (ep.scal && ep.scal[S_DONE] != 0.0) return;
     const int64_t g8 = (groups + 7) / 8;
     for (int64_t b = blockIdx.x; b < launch; b += gridDim.x) {
@@ -394,7 +400,7 @@ kct_status fwd_typed(Plan &p, const void *pad, void *proj, const Epilogue &ep, h
     // 32-bit byte offsets when both padded copies fit in 4 GiB.
     const bool small = 2 * p.pad.vox * int64_t(sizeof(TV)) < int64_t(0xffffffffLL);
 #define KCT_FWD_LAUNCH(OFF_T, PF)                                                                                  \
-    hipLaunchKernelGGL((k_forward<TV, TP, OFF_T, PF>), dim3(grid), dim3(256), 0, st, static_cast<const TV *>(pad), \
+    hipLaunchKernelGGL((k_forward<TV, TP, OFF_T, PF>), dim3(grid), dim3(p.fwd_wave_angles > 4 ? 64 * p.fwd_wave_angles : 256), 0, st, static_cast<const TV *>(pad), \
                        static_cast<TP *>(proj), p.d_tab, p.gp, p.pad, tiles_u, tiles_v, p.fwd_lane_u,                 \
                        p.fwd_wave_angles, p.fwd_angle_block, groups, launch, ep)
     if (small) {

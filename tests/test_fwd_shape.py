@@ -2,8 +2,10 @@
 
 The plan picks the wave patch from the ray spacing at the rotation axis
 (32 x 2 pixels when neighbouring rays are a voxel or more apart, else
-16 x 4), traces one patch at 4 neighbouring angles per workgroup, and widens
-16-bit volumes into FP32 padded copies while those fit in 4 GiB.  The
+16 x 4), widens 16-bit volumes into FP32 padded copies while those fit in
+4 GiB, and traces one patch at 4 neighbouring angles per workgroup in blocks
+of 8 angles, or, where the padded copies stay 16-bit, at 8 angles per
+workgroup in blocks of 16.  The
 choice is computed on the host, without a device; the environment overrides
 are checked too."""
 import ctypes
@@ -32,8 +34,9 @@ def _shape(gd):
     # 2 x 514^3 FP32 padded copies (1.09 GB) fit in 4 GiB.
     ("torso512", (16, 4, 8, 1)),
     # 0.1 mm pixels at magnification 5.33: rays 18.75 um apart, voxels
-    # 10 um; 2 x 1502^3 FP32 copies (27 GB) would not fit in 4 GiB.
-    ("muct1500", (32, 4, 8, 0)),
+    # 10 um; 2 x 1502^3 FP32 copies (27 GB) would not fit in 4 GiB, so the
+    # copies stay 16-bit and a workgroup traces 8 angles.
+    ("muct1500", (32, 8, 16, 0)),
     # 1 mm pixels at 1.5: rays 0.67 mm apart, voxels 1 mm.
     ("cgls32", (16, 4, 8, 1)),
 ])
@@ -64,3 +67,7 @@ def test_environment_overrides(monkeypatch):
     monkeypatch.setenv("KCT_FWD_WAVE_ANGLES", "2")
     monkeypatch.setenv("KCT_FWD_ANGLE_BLOCK", "12")
     assert _shape(gd)[:3] == (16, 4, 8)
+    # A block holds at least one workgroup's angles.
+    monkeypatch.setenv("KCT_FWD_WAVE_ANGLES", "16")
+    monkeypatch.setenv("KCT_FWD_ANGLE_BLOCK", "8")
+    assert _shape(gd)[1:3] == (16, 16)

@@ -128,8 +128,8 @@ def test_forward_gather_depths_agree_bitwise(kct, name, monkeypatch):
 
 @pytest.mark.parametrize("name,lanes", [("ragged", "16"), ("ragged", "64"), ("face_planes", "32"), ("muct_crop", "16")])
 def test_forward_workgroup_shapes_agree_bitwise(kct, name, lanes, monkeypatch):
-    """Workgroups of one angle (64 x 4 pixels) and of one wave patch at 4
-    angles (KCT_FWD_WAVE_ANGLES), in angle blocks of 4, 8, 16 or 32
+    """Workgroups of one angle (64 x 4 pixels) and of one wave patch at 4, 8
+    or 16 angles (KCT_FWD_WAVE_ANGLES), in angle blocks of 4, 8, 16 or 32
     (KCT_FWD_ANGLE_BLOCK; both read at plan creation), trace every ray with
     the same code: the projections are bitwise equal, also for the angles of
     a last, partly filled block (23 angles) and ragged detector edges."""
@@ -137,7 +137,8 @@ def test_forward_workgroup_shapes_agree_bitwise(kct, name, lanes, monkeypatch):
     x = torch.from_numpy(synth.random_volume(tuple(gd[k] for k in ("nz", "ny", "nx")), 9)).to(DEV)
     monkeypatch.setenv("KCT_FWD_LANES_U", lanes)
     outs = []
-    for wa, ab in (("1", "8"), ("4", "8"), ("4", "4"), ("4", "16"), ("1", "32"), ("4", "32")):
+    for wa, ab in (("1", "8"), ("4", "8"), ("4", "4"), ("4", "16"), ("1", "32"), ("4", "32"), ("8", "16"),
+                   ("8", "8"), ("16", "32")):
         monkeypatch.setenv("KCT_FWD_WAVE_ANGLES", wa)
         monkeypatch.setenv("KCT_FWD_ANGLE_BLOCK", ab)
         plan = kct.Plan(kct.Geometry.from_dict(gd))
