@@ -170,16 +170,23 @@ void choose_fwd_shape(Plan &p)
     // MALL-resident and the deeper loop's extra selects cost more: 256^3,
     // 17.4 against 18.3 ms).
     p.fwd_prefetch = p.fwd_pad_f32 ? 1 : 2;
-    // Angles per workgroup, one wave each: where the padded copies stay
-    // 16-bit, 8 angles (512 threads) in work-order blocks of 16, so that each
-    // line a wave gathers serves twice as many waves of the same CU while it
-    // is in L1 (1500^3: 2.90 against 3.32 s; 16 angles: 3.16 s).  The
-    // FP32-copy volumes, resident in L2 and the MALL, keep 4 angles, which
-    // leave room for a fifth wave per SIMD (256^3: 17.3 against 17.7 ms with
-    // 8 angles and 23.4 ms with 16).
+    // Where the padded copies stay 16-bit (volumes far larger than L2 and
+    // the MALL):
+    // - 8 angles per workgroup (512 threads), so that each line a wave
+    //   gathers serves twice as many waves of the same CU (1500^3: 2.90
+    //   against 3.32 s; 16 angles: 3.16 s);
+    // - work-order blocks of 128 angles, handed to the XCDs in turns of half
+    //   a row band each, so that all XCDs work on neighbouring detector rows
+    //   of the same angles at a time and the few z-slices those rays cross
+    //   stay in the MALL (1500^3: 2.47-2.49 against 2.90 s with each XCD
+    //   taking one eighth of the work in order; blocks of 64 or 256: 2.48 s).
+    // The FP32-copy volumes, resident in L2 and the MALL, keep 4 angles
+    // (a fifth wave per SIMD), blocks of 8 and one eighth per XCD (256^3:
+    // 17.3 ms; 8 angles 17.7 ms, 16 angles 23.4 ms).
     if (!p.fwd_pad_f32) {
         p.fwd_wave_angles = 8;
-        p.fwd_angle_block = 16;
+        p.fwd_angle_block = 128;
+        p.fwd_xcd_chunk = 0;
     }
     // Tuning override: KCT_FWD_PREFETCH selects how many segments ahead the
     // forward loop gathers (0, 1 or 2).
@@ -200,12 +207,16 @@ void choose_fwd_shape(Plan &p)
         const int wa = std::atoi(e);
         if (wa == 1 || wa == 4 || wa == 8 || wa == 16) p.fwd_wave_angles = wa;
     }
-    // Tuning override: angles per block of the forward work order.
+    // Tuning override: angles per block of the forward work order (a power
+    // of two, 4 to 4096).
     if (const char *e = std::getenv("KCT_FWD_ANGLE_BLOCK")) {
         const int ab = std::atoi(e);
-        if (ab == 4 || ab == 8 || ab == 16 || ab == 32) p.fwd_angle_block = ab;
+        if (ab >= 4 && ab <= 4096 && (ab & (ab - 1)) == 0) p.fwd_angle_block = ab;
     }
     if (p.fwd_angle_block < p.fwd_wave_angles) p.fwd_angle_block = p.fwd_wave_angles;
+    // Tuning override: logical tiles an XCD takes per turn (-1: one eighth
+    // of all, in order; 0: half a row band; N > 0: N).
+    if (const char *e = std::getenv("KCT_FWD_XCD_CHUNK")) p.fwd_xcd_chunk = std::max(-1LL, std::atoll(e));
 }
 
 } // namespace kct

@@ -115,6 +115,7 @@ struct Plan {
     int fwd_lane_u = 16;          // forward wave patch: lane_u x (64 / lane_u) rays (64, 32 or 16)
     int fwd_wave_angles = 4;      // angles per forward workgroup: 1 (64 x 4 pixels) or 4, 8, 16 (one patch each)
     int fwd_angle_block = 8;      // forward work order: angles per block (4, 8, 16 or 32)
+    int64_t fwd_xcd_chunk = -1;   // forward: logical tiles per XCD turn: -1 one eighth each, 0 half a row band
     bool fwd_pad_f32 = true;      // forward: 16-bit volumes are padded into FP32 copies (small volumes)
     bool bwd_acc_lds = true;      // back projector keeps per-voxel sums in LDS
     bool bwd_sparse_ok = false;   // every voxel footprint narrower than a pixel (u and v)

@@ -346,21 +346,30 @@ __device__ inline void fwd_tile(const TV *__restrict__ vpad, TP *__restrict__ pr
 // A dispatch holds fewer than 2^32 work-items, so large problems launch at
 // most FWD_MAX_BLOCKS workgroups (a multiple of 8) and each takes the tiles
 // blockIdx.x, blockIdx.x + gridDim.x, ...  The physical index b keeps its XCD
-// (b mod 8) on every pass; the logical tile is (b mod 8) * g8 + b / 8, so each
-// XCD works through one contiguous eighth of the tiles (neighbouring angles
-// and detector rows share its L2).
+// (b mod 8) on every pass.  The XCDs take the logical tiles in turns of
+// xcd_chunk consecutive tiles: with xcd_chunk = launch / 8 each XCD works
+// through one contiguous eighth (neighbouring angles and detector rows share
+// its L2); with half a row band per turn all XCDs work on neighbouring rows
+// of the same angle block at once (their rays cross the same few z-slices,
+// which stay in the MALL).
 template <typename TV, typename TP, typename OFF, int DEPTH>
 __global__ __launch_bounds__(1024) void k_forward(const TV *__restrict__ vpad, TP *__restrict__ proj,
                                                  const AngleGeo *__restrict__ tab, GeoParams g, PadLayout pl,
                                                  int tiles_u, int tiles_v, int lane_u, int wave_angles,
                                                  int angle_block, int64_t groups, int64_t launch,
-                                                 Epilogue ep)
+                                                 int64_t xcd_chunk, Epilogue ep)
 {
     __shared__ double red[16];
     if (ep.scal && ep.scal[S_DONE] != 0.0) return;
-    const int64_t g8 = (groups + 7) / 8;
+    const int64_t g8 = launch >> 3;
+    const int64_t C = xcd_chunk > 0 ? xcd_chunk : g8;
     for (int64_t b = blockIdx.x; b < launch; b += gridDim.x) {
-        const int64_t logical = (b & 7) * g8 + (b >> 3);
+        // The k-th workgroup of XCD x takes chunk q = k / C: logical tiles
+        // q * 8C + x * w + k mod C, w = min(C, g8 - q * C) (a bijection onto
+        // [0, launch)).
+        const int64_t k = b >> 3, q = k / C, r = k - q * C;
+        const int64_t w = min(C, g8 - q * C);
+        const int64_t logical = q * 8 * C + (b & 7) * w + r;
         if (logical >= groups) continue;
         fwd_tile<TV, TP, OFF, DEPTH>(vpad, proj, tab, g, pl, tiles_u, tiles_v, lane_u, wave_angles, angle_block,
                                          logical, ep, red);
@@ -396,13 +405,16 @@ kct_status fwd_typed(Plan &p, const void *pad, void *proj, const Epilogue &ep, h
     int tiles_u = 0, tiles_v = 0;
     const int64_t groups = fwd_tiling(p, tiles_u, tiles_v);
     const int64_t launch = ((groups + 7) / 8) * 8;
+    const int64_t per_band = int64_t(p.fwd_angle_block / p.fwd_wave_angles) * tiles_u;
+    const int64_t xcd_chunk = p.fwd_xcd_chunk > 0 ? p.fwd_xcd_chunk
+                              : p.fwd_xcd_chunk < 0 ? 0 : std::max<int64_t>(1, per_band / 2);
     const unsigned grid = unsigned(std::min<int64_t>(launch, FWD_MAX_BLOCKS));
     // 32-bit byte offsets when both padded copies fit in 4 GiB.
     const bool small = 2 * p.pad.vox * int64_t(sizeof(TV)) < int64_t(0xffffffffLL);
 #define KCT_FWD_LAUNCH(OFF_T, PF)                                                                                  \
     hipLaunchKernelGGL((k_forward<TV, TP, OFF_T, PF>), dim3(grid), dim3(p.fwd_wave_angles > 4 ? 64 * p.fwd_wave_angles : 256), 0, st, static_cast<const TV *>(pad), \
                        static_cast<TP *>(proj), p.d_tab, p.gp, p.pad, tiles_u, tiles_v, p.fwd_lane_u,                 \
-                       p.fwd_wave_angles, p.fwd_angle_block, groups, launch, ep)
+                       p.fwd_wave_angles, p.fwd_angle_block, groups, launch, xcd_chunk, ep)
     if (small) {
         if (p.fwd_prefetch == 2) KCT_FWD_LAUNCH(uint32_t, 2);
         else if (p.fwd_prefetch == 1) KCT_FWD_LAUNCH(uint32_t, 1);

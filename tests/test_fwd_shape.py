@@ -5,7 +5,7 @@ The plan picks the wave patch from the ray spacing at the rotation axis
 16 x 4), widens 16-bit volumes into FP32 padded copies while those fit in
 4 GiB, and traces one patch at 4 neighbouring angles per workgroup in blocks
 of 8 angles, or, where the padded copies stay 16-bit, at 8 angles per
-workgroup in blocks of 16.  The
+workgroup in blocks of 128.  The
 choice is computed on the host, without a device; the environment overrides
 are checked too."""
 import ctypes
@@ -36,7 +36,7 @@ def _shape(gd):
     # 0.1 mm pixels at magnification 5.33: rays 18.75 um apart, voxels
     # 10 um; 2 x 1502^3 FP32 copies (27 GB) would not fit in 4 GiB, so the
     # copies stay 16-bit and a workgroup traces 8 angles.
-    ("muct1500", (32, 8, 16, 0)),
+    ("muct1500", (32, 8, 128, 0)),
     # 1 mm pixels at 1.5: rays 0.67 mm apart, voxels 1 mm.
     ("cgls32", (16, 4, 8, 1)),
 ])

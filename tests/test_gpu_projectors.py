@@ -129,18 +129,22 @@ def test_forward_gather_depths_agree_bitwise(kct, name, monkeypatch):
 @pytest.mark.parametrize("name,lanes", [("ragged", "16"), ("ragged", "64"), ("face_planes", "32"), ("muct_crop", "16")])
 def test_forward_workgroup_shapes_agree_bitwise(kct, name, lanes, monkeypatch):
     """Workgroups of one angle (64 x 4 pixels) and of one wave patch at 4, 8
-    or 16 angles (KCT_FWD_WAVE_ANGLES), in angle blocks of 4, 8, 16 or 32
-    (KCT_FWD_ANGLE_BLOCK; both read at plan creation), trace every ray with
+    or 16 angles (KCT_FWD_WAVE_ANGLES), in angle blocks of 4 to 128
+    (KCT_FWD_ANGLE_BLOCK), handed to the XCDs in eighths, half row bands or
+    turns of 3 tiles (KCT_FWD_XCD_CHUNK; all read at plan creation), trace
+    every ray with
     the same code: the projections are bitwise equal, also for the angles of
     a last, partly filled block (23 angles) and ragged detector edges."""
     gd = _geoms()[name]
     x = torch.from_numpy(synth.random_volume(tuple(gd[k] for k in ("nz", "ny", "nx")), 9)).to(DEV)
     monkeypatch.setenv("KCT_FWD_LANES_U", lanes)
     outs = []
-    for wa, ab in (("1", "8"), ("4", "8"), ("4", "4"), ("4", "16"), ("1", "32"), ("4", "32"), ("8", "16"),
-                   ("8", "8"), ("16", "32")):
+    for wa, ab, xc in (("1", "8", "-1"), ("4", "8", "-1"), ("4", "4", "-1"), ("4", "16", "-1"), ("1", "32", "-1"),
+                       ("4", "32", "-1"), ("8", "16", "-1"), ("8", "8", "-1"), ("16", "32", "-1"), ("8", "128", "0"),
+                       ("4", "64", "0"), ("8", "16", "3")):
         monkeypatch.setenv("KCT_FWD_WAVE_ANGLES", wa)
         monkeypatch.setenv("KCT_FWD_ANGLE_BLOCK", ab)
+        monkeypatch.setenv("KCT_FWD_XCD_CHUNK", xc)
         plan = kct.Plan(kct.Geometry.from_dict(gd))
         outs.append(plan.forward(x))
         torch.cuda.synchronize()
