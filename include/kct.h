@@ -118,13 +118,13 @@ typedef struct kct_plan kct_plan;
  *                                 wave each (8 where the padded copies stay
  *                                 16-bit, else 4)
  *   KCT_FWD_ANGLE_BLOCK  4 ... 4096 (powers of two)  angles per block of
- *                                 the forward's work order (128 where the
- *                                 padded copies stay 16-bit, else 8; at least
- *                                 the angles per workgroup)
+ *                                 the forward's work order (128 with at least
+ *                                 256 angles, else 8; at least the angles
+ *                                 per workgroup)
  *   KCT_FWD_XCD_CHUNK    -1, 0, N  forward tiles an XCD takes per turn: -1
  *                                 one eighth of all in order, 0 half a row
- *                                 band of the angle block (where the padded
- *                                 copies stay 16-bit; else -1), N tiles
+ *                                 band of the angle block (with at least 256
+ *                                 angles; else -1), N tiles
  *   KCT_FWD_PAD_F32      0 or 1   the forward widens a 16-bit volume into FP32
  *                                 padded copies (1 while those fit in 4 GiB)
  *   KCT_BWD_KZ           1, 8, 16 voxels per back-projector thread along z

@@ -170,24 +170,26 @@ void choose_fwd_shape(Plan &p)
     // MALL-resident and the deeper loop's extra selects cost more: 256^3,
     // 17.4 against 18.3 ms).
     p.fwd_prefetch = p.fwd_pad_f32 ? 1 : 2;
-    // Where the padded copies stay 16-bit (volumes far larger than L2 and
-    // the MALL):
-    // - 8 angles per workgroup (512 threads), so that each line a wave
-    //   gathers serves twice as many waves of the same CU (1500^3: 2.90
-    //   against 3.32 s; 16 angles: 3.16 s);
-    // - work-order blocks of 128 angles, handed to the XCDs in turns of half
-    //   a row band each, so that all XCDs work on neighbouring detector rows
-    //   of the same angles at a time and the few z-slices those rays cross
-    //   stay in the MALL (1500^3: 2.47-2.49 against 2.90 s with each XCD
-    //   taking one eighth of the work in order; blocks of 64 or 256: 2.48 s).
-    // The FP32-copy volumes, resident in L2 and the MALL, keep 4 angles
-    // (a fifth wave per SIMD), blocks of 8 and one eighth per XCD (256^3:
-    // 17.3 ms; 8 angles 17.7 ms, 16 angles 23.4 ms).
-    if (!p.fwd_pad_f32) {
-        p.fwd_wave_angles = 8;
+    // Work order: with at least FWD_ORDER_MIN_ANGLES angles, blocks of 128
+    // angles handed to the XCDs in turns of half a row band each, so that
+    // all XCDs work on neighbouring detector rows of the same angles at a
+    // time and the few z-slices those rays cross stay in the MALL; else
+    // blocks of 8 with each XCD taking one eighth of the work in order.
+    // 1500^3: 2.47-2.49 against 2.90 s (blocks of 64 or 256: 2.48 s);
+    // 512^3 / 720 x 1024 x 768: 225 against 241 ms; 256^3 / 360 x 512^2:
+    // 17.1 against 17.3 ms.
+    if (g.n_angles >= FWD_ORDER_MIN_ANGLES) {
         p.fwd_angle_block = 128;
         p.fwd_xcd_chunk = 0;
     }
+    // Where the padded copies stay 16-bit (volumes far larger than L2 and
+    // the MALL), 8 angles per workgroup (512 threads), so that each line a
+    // wave gathers serves twice as many waves of the same CU (1500^3, with
+    // blocks of 16: 2.90 against 3.32 s; 16 angles: 3.16 s).  The FP32-copy
+    // volumes keep 4 angles, which leave room for a fifth wave per SIMD
+    // (256^3: 17.3 ms; 8 angles 17.7 ms, 16 angles 23.4 ms; 512^3 with
+    // blocks of 128: 225 ms, 8 angles 243 ms).
+    if (!p.fwd_pad_f32) p.fwd_wave_angles = 8;
     // Tuning override: KCT_FWD_PREFETCH selects how many segments ahead the
     // forward loop gathers (0, 1 or 2).
     if (const char *e = std::getenv("KCT_FWD_PREFETCH")) {

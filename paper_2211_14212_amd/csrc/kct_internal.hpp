@@ -175,5 +175,9 @@ bool dtype_ok(int dt);
 
 } // namespace kct
 
+// Plans with at least this many angles take the forward work order of
+// 128-angle blocks handed to the XCDs in half row bands.
+constexpr int FWD_ORDER_MIN_ANGLES = 256;
+
 // The opaque handle of kct.h is the plan itself.
 struct kct_plan : public kct::Plan {};

@@ -646,6 +646,12 @@ void sa_views(kct_state &s)
         // forward uses the one-angle shape (46.8 against 42.3 ms per
         // 10-subset iteration on 256^3 / 360 x 512^2).
         if (m > 1) v.fwd_wave_angles = 1;
+        // A subset too small for the large-plan work order takes the small
+        // one (a block of 128 angles would hold mostly empty tiles).
+        if (v.gp.na < FWD_ORDER_MIN_ANGLES && v.fwd_angle_block > 8) {
+            v.fwd_angle_block = std::max(8, v.fwd_wave_angles);
+            v.fwd_xcd_chunk = -1;
+        }
     }
 }
 

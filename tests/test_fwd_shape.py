@@ -3,9 +3,9 @@
 The plan picks the wave patch from the ray spacing at the rotation axis
 (32 x 2 pixels when neighbouring rays are a voxel or more apart, else
 16 x 4), widens 16-bit volumes into FP32 padded copies while those fit in
-4 GiB, and traces one patch at 4 neighbouring angles per workgroup in blocks
-of 8 angles, or, where the padded copies stay 16-bit, at 8 angles per
-workgroup in blocks of 128.  The
+4 GiB, and traces one patch at 4 neighbouring angles per workgroup (8 where
+the padded copies stay 16-bit), in work-order blocks of 128 angles when the
+plan has at least 256 angles, else of 8.  The
 choice is computed on the host, without a device; the environment overrides
 are checked too."""
 import ctypes
@@ -30,9 +30,9 @@ def _shape(gd):
 
 @pytest.mark.parametrize("name,expect", [
     # 0.4 mm pixels at magnification 1.5: rays 0.27 mm apart, voxels 0.5 mm.
-    ("medical256", (16, 4, 8, 1)),
+    ("medical256", (16, 4, 128, 1)),
     # 2 x 514^3 FP32 padded copies (1.09 GB) fit in 4 GiB.
-    ("torso512", (16, 4, 8, 1)),
+    ("torso512", (16, 4, 128, 1)),
     # 0.1 mm pixels at magnification 5.33: rays 18.75 um apart, voxels
     # 10 um; 2 x 1502^3 FP32 copies (27 GB) would not fit in 4 GiB, so the
     # copies stay 16-bit and a workgroup traces 8 angles.
@@ -66,7 +66,7 @@ def test_environment_overrides(monkeypatch):
     monkeypatch.setenv("KCT_FWD_LANES_U", "48")
     monkeypatch.setenv("KCT_FWD_WAVE_ANGLES", "2")
     monkeypatch.setenv("KCT_FWD_ANGLE_BLOCK", "12")
-    assert _shape(gd)[:3] == (16, 4, 8)
+    assert _shape(gd)[:3] == (16, 4, 128)
     # A block holds at least one workgroup's angles.
     monkeypatch.setenv("KCT_FWD_WAVE_ANGLES", "16")
     monkeypatch.setenv("KCT_FWD_ANGLE_BLOCK", "8")
