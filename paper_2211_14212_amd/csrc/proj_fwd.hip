@@ -75,7 +75,7 @@ __global__ __launch_bounds__(256) void k_pad_volume(const TIN *__restrict__ in, 
 // Deterministic workgroup sum of one double per thread (256, 512 or 1024
 // threads; `red` holds one double per wave): waves summed in groups of four,
 // the groups in order.
-__device__ inline double block_sum_256(double v, double *red)
+__device__ inline double block_sum(double v, double *red)
 {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -338,7 +338,7 @@ __device__ inline void fwd_tile(const TV *__restrict__ vpad, TP *__restrict__ pr
         outv = to_f32(st);
     }
     if (ep.partials) {
-        const double s = block_sum_256(double(outv) * double(outv), red);
+        const double s = block_sum(double(outv) * double(outv), red);
         if (threadIdx.x == 0) ep.partials[logical] = s;
     }
 }
@@ -352,6 +352,8 @@ __device__ inline void fwd_tile(const TV *__restrict__ vpad, TP *__restrict__ pr
 // its L2); with half a row band per turn all XCDs work on neighbouring rows
 // of the same angle block at once (their rays cross the same few z-slices,
 // which stay in the MALL).
+// Workgroups of 256 threads, or 64 per angle with 8 or 16 angles each (the
+// bound lets the compiler budget registers for up to 1024).
 template <typename TV, typename TP, typename OFF, int DEPTH>
 __global__ __launch_bounds__(1024) void k_forward(const TV *__restrict__ vpad, TP *__restrict__ proj,
                                                  const AngleGeo *__restrict__ tab, GeoParams g, PadLayout pl,
@@ -409,10 +411,11 @@ kct_status fwd_typed(Plan &p, const void *pad, void *proj, const Epilogue &ep, h
     const int64_t xcd_chunk = p.fwd_xcd_chunk > 0 ? p.fwd_xcd_chunk
                               : p.fwd_xcd_chunk < 0 ? 0 : std::max<int64_t>(1, per_band / 2);
     const unsigned grid = unsigned(std::min<int64_t>(launch, FWD_MAX_BLOCKS));
+    const unsigned threads = unsigned(p.fwd_wave_angles > 4 ? 64 * p.fwd_wave_angles : 256);
     // 32-bit byte offsets when both padded copies fit in 4 GiB.
     const bool small = 2 * p.pad.vox * int64_t(sizeof(TV)) < int64_t(0xffffffffLL);
 #define KCT_FWD_LAUNCH(OFF_T, PF)                                                                                  \
-    hipLaunchKernelGGL((k_forward<TV, TP, OFF_T, PF>), dim3(grid), dim3(p.fwd_wave_angles > 4 ? 64 * p.fwd_wave_angles : 256), 0, st, static_cast<const TV *>(pad), \
+    hipLaunchKernelGGL((k_forward<TV, TP, OFF_T, PF>), dim3(grid), dim3(threads), 0, st, static_cast<const TV *>(pad), \
                        static_cast<TP *>(proj), p.d_tab, p.gp, p.pad, tiles_u, tiles_v, p.fwd_lane_u,                 \
                        p.fwd_wave_angles, p.fwd_angle_block, groups, launch, xcd_chunk, ep)
     if (small) {
