@@ -168,15 +168,17 @@ def _cpu_model():
 
 def counter_entry(workload, kernel_key, digest):
     """The committed rocprofv3 counter summary of one projector kernel, if it
-    was taken on the current kernel source; else None.  It holds the HBM bytes
-    per launch (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), the L2
-    hit rate (TCC_HIT / (TCC_HIT + TCC_MISS)) and the VALU instructions per
-    unit of work (SQ_INSTS_VALU over nonzeros or voxel-views)."""
+    was taken on the current kernel source and the current launch-shape
+    choices (`api.hip`, where the plan picks them); else None.  It holds the
+    HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated on a plain
+    copy), the L2 hit rate (TCC_HIT / (TCC_HIT + TCC_MISS)) and the VALU
+    instructions per unit of work (SQ_INSTS_VALU over nonzeros or
+    voxel-views)."""
     path = os.path.join(ROOT, "profiles", f"{workload}_counters.json")
     if not os.path.exists(path):
         return None
     k = json.load(open(path)).get("kernels", {}).get(kernel_key)
-    if not k or k.get("src_digest") != digest:
+    if not k or k.get("src_digest") != digest or k.get("api_digest") != src_digest("api.hip"):
         return None
     return k
 
