@@ -12,7 +12,8 @@ tables, whose build waits for the device) are made by a worker thread as
 requests arrive, off the serving loop.  A request leaves when its last
 iteration has run on the device; its memory is freed and queued requests are
 admitted in its place.  A request that needs more memory than the whole
-budget is rejected on arrival.  Each request's result is bitwise the
+budget is rejected when its plan is ready, and so is one whose plan cannot
+be made (an invalid geometry; the result carries the library's message).  Each request's result is bitwise the
 same as a solo kct_solve of it (deterministic kernels, private buffers).
 Admission is first-come first-served by default; ``policy="sjf"`` admits the
 queued request with the least work first (ray-iterations, the cost of its
@@ -72,7 +73,8 @@ class Result:
     x: torch.Tensor | None
     history: torch.Tensor | None
     cancelled: bool = False
-    rejected: bool = False   # needs more memory than the whole budget
+    rejected: bool = False   # needs more memory than the whole budget, or its plan failed
+    error: str | None = None  # why the plan failed (a rejected request only)
 
     @property
     def latency(self) -> float:
@@ -165,7 +167,9 @@ class Server:
                     for req in queue:
                         if req.id in self._cancel:
                             results[req.id] = Result(req.id, req.arrival, now, now, None, None, cancelled=True)
-                            plans.pop(req.id).result().close()
+                            fut = plans.pop(req.id)
+                            if fut.exception() is None:
+                                fut.result().close()
                             self.log.append(("cancel", req.id, now, used))
                         else:
                             keep.append(req)
@@ -183,6 +187,14 @@ class Server:
                     req = queue[i]
                     if not plans[req.id].done():
                         break
+                    exc = plans[req.id].exception()
+                    if exc is not None:  # e.g. an invalid geometry: the request alone fails
+                        del queue[i]
+                        plans.pop(req.id)
+                        t = time.perf_counter() - t0
+                        results[req.id] = Result(req.id, req.arrival, t, t, None, None, rejected=True, error=str(exc))
+                        self.log.append(("error", req.id, t, used))
+                        continue
                     plan = plans[req.id].result()
                     need = request_bytes(plan, req)
                     if need > self.budget:

@@ -2,6 +2,8 @@
 same alone and in the mix; admission never exceeds the HBM budget; cancelling
 a request mid-flight leaves the others bitwise unchanged; a small request is
 spot-checked against the FP64 oracle."""
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -110,6 +112,22 @@ def test_oversized_request_rejected(stream):
     assert serve.summarize(res)["n"] == len(reqs) - len(big)
 
 
+def test_request_with_invalid_geometry_rejected(stream):
+    """A request whose plan cannot be made (its source orbit passes through
+    the volume) is rejected with the library's message; the server keeps
+    serving the others."""
+    serve, reqs = stream
+    few = reqs[:3]
+    g = few[1].geom
+    bad = dataclasses.replace(few[1], id=1000, geom=dataclasses.replace(g, dso=0.25 * g.nx * g.vx, dsd=2.0 * g.nx * g.vx))
+    srv = serve.Server(budget_bytes=200e9, max_active=3, keep_results=False, policy="fifo")
+    res = srv.run(few + [bad])
+    by_id = {r.id: r for r in res}
+    assert by_id[1000].rejected and "source orbit" in (by_id[1000].error or ""), by_id[1000]
+    assert all(not by_id[r.id].rejected and not by_id[r.id].cancelled for r in few)
+    assert [e[1] for e in srv.log if e[0] == "error"] == [1000]
+
+
 def test_cancel_leaves_others_bitwise(stream):
     serve, reqs = stream
     victim, early = reqs[1].id, reqs[-1].id
@@ -138,7 +156,6 @@ def _host_requests(serve, reqs, ids):
     the oracle (the request's phantom, FP64 forward projection, seeded Poisson
     counts at I0 = 1e5, rounded to FP32), so that no oracle input comes from
     the GPU; the other requests keep their GPU-made projections."""
-    import dataclasses
 
     import synth
 
