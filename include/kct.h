@@ -135,13 +135,16 @@ typedef struct kct_plan kct_plan;
  *                                 every voxel's footprint is narrower than a
  *                                 pixel, which it needs; 1 is ignored
  *                                 elsewhere) or the voxel-driven one
+ *   KCT_BWD_XCD_CHUNK    -1 or N  back-projector tiles an XCD takes per turn
+ *                                 (-1: one contiguous eighth per XCD; by
+ *                                 default whole rows of tiles, at least 32)
  *   KCT_BWD_TEST_PW_MAX  >= 1     test hook: caps the back projector's per-tile
  *                                 patch width, so that the footprint overflow
  *                                 report (kct_plan_check, history code 4) can
  *                                 be exercised; the sums are then truncated
- * The forward settings give bitwise-equal projections; they regroup only
- * the per-workgroup partial sums that the solvers reduce.  KCT_BWD_SPLIT
- * changes the order of the FP32 sums.
+ * The forward settings and KCT_BWD_XCD_CHUNK give bitwise-equal outputs;
+ * they regroup only the per-workgroup partial sums that the solvers reduce.
+ * KCT_BWD_SPLIT changes the order of the FP32 sums.
  */
 kct_status kct_plan_create(const kct_geometry *geom, int device, kct_plan **out);
 

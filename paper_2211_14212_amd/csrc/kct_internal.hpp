@@ -120,6 +120,7 @@ struct Plan {
     bool bwd_acc_lds = true;      // back projector keeps per-voxel sums in LDS
     bool bwd_sparse_ok = false;   // every voxel footprint narrower than a pixel (u and v)
     bool bwd_rays = false;        // ray-driven back projector (needs bwd_sparse_ok)
+    int64_t bwd_xcd_chunk = -1;   // back projector: tiles per XCD turn (-1: one eighth per XCD)
     size_t bwd_lds = 0;
     int64_t n_vox() const { return int64_t(gp.nx) * gp.ny * gp.nz; }
     int64_t n_ray() const { return int64_t(gp.na) * gp.nv * gp.nu; }

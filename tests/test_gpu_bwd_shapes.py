@@ -80,6 +80,7 @@ SHAPES = [
 
 @pytest.mark.parametrize("name,kz,acc,split,rays", SHAPES)
 def test_backward_shape_matches_oracle(kct, name, kz, acc, split, rays, monkeypatch):
+    monkeypatch.delenv("KCT_BWD_XCD_CHUNK", raising=False)
     for var, val in (("KCT_BWD_KZ", kz), ("KCT_BWD_ACC", acc), ("KCT_BWD_SPLIT", split), ("KCT_BWD_RAYS", rays)):
         if val is not None:
             monkeypatch.setenv(var, val)
@@ -89,6 +90,31 @@ def test_backward_shape_matches_oracle(kct, name, kz, acc, split, rays, monkeypa
     shape = _check(kct, _geoms()[name], 211)
     if kz is not None:
         assert shape["kz"] == int(kz)
+
+
+@pytest.mark.parametrize("name,rays", [("medical_crop", "0"), ("muct_crop", None)])
+def test_backward_xcd_turns_agree_bitwise(kct, name, rays, monkeypatch):
+    """The order in which the XCDs take the tiles (KCT_BWD_XCD_CHUNK: one
+    contiguous eighth each, or turns of 1, 3 or 32 tiles) changes no voxel's
+    sum: each tile's sums are formed by one workgroup alone."""
+    for var in ("KCT_BWD_KZ", "KCT_BWD_ACC", "KCT_BWD_SPLIT"):
+        monkeypatch.delenv(var, raising=False)
+    if rays is None:
+        monkeypatch.delenv("KCT_BWD_RAYS", raising=False)
+    else:
+        monkeypatch.setenv("KCT_BWD_RAYS", rays)
+    gd = _geoms()[name]
+    y = torch.from_numpy(synth.random_projections(tuple(
+        (len(gd["angles"]), gd["nv"], gd["nu"])), 214)).to(DEV)
+    outs = []
+    for c in ("-1", "1", "3", "32"):
+        monkeypatch.setenv("KCT_BWD_XCD_CHUNK", c)
+        plan = kct.Plan(kct.Geometry.from_dict(gd))
+        outs.append(plan.backproject(y))
+        torch.cuda.synchronize()
+        plan.close()
+    for o in outs[1:]:
+        assert torch.equal(outs[0], o)
 
 
 def test_backward_default_shape_mid_volume(kct, monkeypatch):
