@@ -46,12 +46,17 @@ __device__ inline float tap(const TP *__restrict__ ya, int nu, int nv, int iu, i
 template <typename TP, typename TV, int KZ>
 __global__ __launch_bounds__(256) void k_interp_bp(const TP *__restrict__ proj, TV *__restrict__ vol,
                                                    const AngleGeo *__restrict__ tab, GeoParams g, int tiles_x,
-                                                   int tiles_y, int64_t groups, Epilogue ep)
+                                                   int tiles_y, int64_t groups, int64_t xcd_chunk, Epilogue ep)
 {
     __shared__ double red[4];
+    // The XCDs (b mod 8) take the tiles in turns of xcd_chunk consecutive
+    // tiles (whole rows, as the matched back projector does), or one
+    // contiguous eighth each when xcd_chunk <= 0.
     const int64_t g8 = (groups + 7) / 8;
     const int64_t b = blockIdx.x;
-    const int64_t logical = (b & 7) * g8 + (b >> 3);
+    const int64_t C = xcd_chunk > 0 ? xcd_chunk : g8;
+    const int64_t k = b >> 3, q = k / C, r = k - q * C;
+    const int64_t logical = q * 8 * C + (b & 7) * min(C, g8 - q * C) + r;
     if (logical >= groups) return;
     if (ep.scal && ep.scal[S_DONE] != 0.0) return;
 
@@ -143,7 +148,7 @@ kct_status ibp_launch(Plan &p, const void *proj, void *vol, const Epilogue &ep, 
     if (launch * 256 >= (int64_t(1) << 32)) return fail(KCT_E_GEOMETRY, "interpolating back projection grid too large");
     hipLaunchKernelGGL((k_interp_bp<TP, TV, IBP_KZ>), dim3(unsigned(launch)), dim3(256), 0, st,
                        static_cast<const TP *>(proj), static_cast<TV *>(vol), p.d_tab, p.gp, int(tiles_x),
-                       int(tiles_y), groups, ep);
+                       int(tiles_y), groups, p.bwd_xcd_chunk, ep);
     return check_hip(hipGetLastError(), "interpolating back projection launch");
 }
 
