@@ -52,8 +52,14 @@ def test_roofline_entry_arithmetic(bench, stats, wl, kname, es):
     assert r["algorithmic_bytes_per_launch"] == alg
     assert r["achieved"] == pytest.approx(alg / (ms / 1000.0) / 1e9, abs=0.05)
     assert r["frac"] == pytest.approx(r["achieved"] / 8000.0, abs=1e-4)
-    # The committed summaries were taken on the current sources.
+    # The counter fields, while the committed summary matches the current
+    # kernel source and launch-shape code (after a kernel change the summary
+    # is stale until the workload is profiled again).
     k = _counters(wl)["kernels"][kname]
+    fresh = bench.counter_entry(wl, kname, bench.src_digest("proj_fwd.hip" if kname == "forward" else "proj_bwd.hip"))
+    if fresh is None:
+        assert r["traffic"] is None and "limiter" not in r
+        pytest.skip(f"the {wl} {kname} counter summary predates the current sources")
     assert r["traffic"] == k["hbm_bytes_per_launch"]
     assert r["valu"]["insts_per_unit"] == pytest.approx(k["valu_insts_per_unit"], abs=1e-4)
     assert r["valu"]["frac"] == pytest.approx(k["valu_insts_per_unit"] * units / (ms / 1000.0) / 1e9 / 614.4,
